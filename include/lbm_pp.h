@@ -1,0 +1,179 @@
+/*
+ * lbm_pp.h -- C-ABI of the MI355X (gfx950) library that advances the
+ * pseudopotential lattice-Boltzmann model of liquid-vapour phase change of
+ * Jaramillo, Mapelli & Cabezas-Gomez, "Pseudopotential Lattice Boltzmann
+ * Method for boiling heat transfer: a mesh refinement procedure".
+ *
+ * One time step (Sec. 2 of the paper) on an nx x ny D2Q9 lattice:
+ *   moments (Eq. DensityAndVelocityRelationToF), Peng-Robinson EOS and
+ *   pseudopotential (Eqs. peng-robinson, psi), interaction, adhesion and
+ *   buoyancy forces (Eqs. shanchen, psi-based-formula, shanchen-walls,
+ *   gravitational_force), the Li forcing and surface-tension terms S, C, Q
+ *   (Eqs. li_source_terms, S, C, Q, Q-psi-based), MRT collision
+ *   (Eq. collisionMRT), streaming with wet-node Zou-He walls (Sec. 2.2),
+ *   and the explicit RK2 update of the energy equation (Eq. energy-equation).
+ * Host helpers cover the mesh-refinement parameter rules of Sec. 3
+ * (Eq. a-deltax, Eq. integral_coexistence_curve, Eq. surface_tension).
+ *
+ * Conventions
+ *  - Every function returns lbm_status; nothing aborts or throws across the
+ *    ABI.  A failing call leaves the context usable unless stated.
+ *  - Device memory is owned by the caller: lbm_buffer_bytes() gives the size
+ *    of ONE device allocation that lbm_create() borrows until lbm_destroy().
+ *    The library itself allocates no device memory.
+ *  - All device work is enqueued on the HIP stream given to lbm_create()
+ *    (NULL = the default stream).  lbm_step() is asynchronous; calls that
+ *    return host data synchronise that stream.  Device-side domain errors
+ *    (density outside (0, 1/b), psi radicand <= 0, T <= 0, NaN) are sticky
+ *    and reported as LBM_E_DOMAIN by the next synchronising call.
+ *  - Host arrays are row-major [ny][nx] (x fastest), y = 0 is the bottom
+ *    row, and are float64 whatever the storage precision.  They are only
+ *    read or written during the call.
+ *  - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef LBM_PP_H
+#define LBM_PP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_E_INVAL = 1,       /* bad argument or parameter set */
+  LBM_E_NOMEM = 2,       /* caller buffer too small, host allocation failed */
+  LBM_E_HIP = 3,         /* HIP runtime error (text in lbm_last_error) */
+  LBM_E_STATE = 4,       /* call out of order (e.g. step before init) */
+  LBM_E_DOMAIN = 5,      /* state left the EOS / pseudopotential domain */
+  LBM_E_UNSUPPORTED = 6  /* valid request this build does not implement */
+} lbm_status;
+
+enum { LBM_FP64 = 0, LBM_FP32_SHIFTED = 1 };          /* storage precision */
+enum { LBM_T_FREE = 0, LBM_T_DIRICHLET = 1, LBM_T_ADIABATIC = 2 };
+
+/* All quantities in lattice units.  lbm_default_params() fills the values
+ * used by the paper's droplet runs (Sec. 4.1) on the ladder EOS a = 2/49. */
+typedef struct lbm_params {
+  int32_t nx, ny;
+  int32_t precision;   /* LBM_FP64 or LBM_FP32_SHIFTED (populations stored
+                          as f_i - w_i rho_ref, collision in float32, EOS,
+                          psi and forces in float64) */
+  int32_t walls;       /* 0: periodic in y; 1: wet-node Zou-He walls on rows
+                          0 and ny-1 (x is always periodic) */
+  int32_t thermal;     /* 1: solve the energy equation */
+  int32_t n_iso;       /* the first n_iso steps keep T frozen (Sec. 4.1) */
+  int32_t t_side_dirichlet; /* 1: columns 0 and nx-1 held at t_side_val */
+  int32_t tile_y;      /* rows per workgroup strip; 0 = library default */
+  double a, b, R, omega, G;      /* Eq. peng-robinson, Eq. psi (G = -1) */
+  double sigma, kappa;           /* Eqs. S and Q */
+  double s_rho, s_e, s_zeta, s_j, s_q;   /* MRT rates; s_nu from eta(rho) */
+  double eta_l, eta_v;           /* Eq. eta-rho: viscosities of both phases */
+  double rho_l, rho_v;           /* phase densities used by eta(rho), lambda(rho) */
+  double gy;                     /* gravity along +y (Eq. gravitational_force) */
+  double cv, lambda_l, lambda_v; /* Sec. 2.3 */
+  double t_side_val;
+  double rho_ref;                /* shift of the float32 storage */
+  int32_t xcd_remap;             /* 1: keep neighbouring tiles on one XCD */
+  int32_t reserved_i[7];
+  double reserved_d[8];
+} lbm_params;
+
+typedef struct lbm_norms_t {
+  double mass;        /* sum of rho over all nodes */
+  double rho_mean;
+  double umax;        /* max |u| */
+  double q_bottom;    /* (1/nx) sum_x lambda dT/dy at y = 0, one-sided 2nd
+                         order (Eq. pool-heat-flux); 0 unless walls */
+  double l1_rho, l2_rho, linf_rho;   /* discrete norms of rho (mean, rms, max) */
+  double l1_T, l2_T, linf_T;
+  int64_t nonfinite;  /* nodes whose rho, u or T is not finite */
+  int64_t step;
+} lbm_norms_t;
+
+const char* lbm_status_string(lbm_status s);
+/* Text of the last error on this context (or of the last failed create when
+ * ctx is NULL).  Valid until the next call on the same context. */
+const char* lbm_last_error(const lbm_ctx* ctx);
+
+void lbm_default_params(lbm_params* p, int32_t nx, int32_t ny);
+/* Check a parameter set without touching the GPU.  LBM_E_INVAL if nx or ny
+ * < 1, walls with ny < 3, a, b <= 0, a rate outside (0, 2), thermal with
+ * cv <= 0 or negative conductivities, rho_l == rho_v, or an unknown precision. */
+lbm_status lbm_validate(const lbm_params* p);
+/* Size in bytes of the device buffer lbm_create() needs for p. */
+lbm_status lbm_buffer_bytes(const lbm_params* p, size_t* bytes);
+
+/* Borrow dev_buf (>= lbm_buffer_bytes, any alignment >= 256 B) on hip_stream
+ * (a hipStream_t, may be NULL).  The device must be current.  On success
+ * *out owns host state only; lbm_destroy() releases it. */
+lbm_status lbm_create(const lbm_params* p, void* dev_buf, size_t bytes, void* hip_stream,
+                      lbm_ctx** out);
+void lbm_destroy(lbm_ctx* ctx);
+
+/* Per-column boundary tables, host arrays of nx entries; NULL keeps the
+ * current table (defaults: rho_w = 1, T kinds FREE, values 0).
+ * rho_w_*: psi-based wall densities rho_w(x) of Eq. psi-based-formula for
+ * rows 0 and ny-1; t_*_kind / t_*_val: temperature condition of rows 0 and
+ * ny-1 (FREE, DIRICHLET value, or ADIABATIC = copy of the adjacent row after
+ * each RK stage).  Must precede lbm_init_fields() to take effect at init. */
+lbm_status lbm_set_boundary(lbm_ctx* ctx, const double* rho_w_bottom, const double* rho_w_top,
+                            const int32_t* t_bottom_kind, const double* t_bottom_val,
+                            const int32_t* t_top_kind, const double* t_top_val);
+
+/* Initial state: f_i = f_i^eq(rho, u) (Eq. EquilibriumDistribution) and T
+ * as given, then (thermal runs) the DIRICHLET values of the boundary tables
+ * applied.  rho and T are required; ux, uy may be NULL (zero).  Resets the
+ * step counter.  Synchronises. */
+lbm_status lbm_init_fields(lbm_ctx* ctx, const double* rho, const double* ux, const double* uy,
+                           const double* T);
+
+/* Advance nsteps >= 0 time steps; asynchronous on the context stream. */
+lbm_status lbm_step(lbm_ctx* ctx, int64_t nsteps);
+
+/* rho, u = (sum f c + F/2)/rho and T at the current step (any pointer may
+ * be NULL).  Synchronises. */
+lbm_status lbm_read_fields(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* T);
+/* Populations f_i at the current step after the wall closure, host array
+ * [9][ny][nx] in the paper's velocity order.  Synchronises. */
+lbm_status lbm_read_populations(lbm_ctx* ctx, double* f);
+/* Global diagnostics (fixed-order float64 reductions).  Synchronises. */
+lbm_status lbm_norms(lbm_ctx* ctx, lbm_norms_t* out);
+
+/* Checkpoint: raw storage of the populations, T and the step counter. */
+lbm_status lbm_state_bytes(const lbm_ctx* ctx, size_t* bytes);
+lbm_status lbm_save_state(lbm_ctx* ctx, void* host, size_t bytes);
+lbm_status lbm_load_state(lbm_ctx* ctx, const void* host, size_t bytes);
+
+/* Wait for the context stream; report sticky device errors. */
+lbm_status lbm_sync(lbm_ctx* ctx);
+int64_t lbm_step_count(const lbm_ctx* ctx);
+
+/* Device time (milliseconds) of the last lbm_step() call, measured with HIP
+ * events recorded on the context stream around its launches.  Waits for the
+ * second event. */
+lbm_status lbm_last_step_time(lbm_ctx* ctx, double* total_ms);
+
+/* ---- host parameter pipeline (Sec. 3); float64, no GPU ----------------- */
+/* T_c of Eq. peng-robinson's a = 0.45724 R^2 T_c^2/p_c, b = 0.0778 R T_c/p_c */
+double lbm_pr_critical_temperature(double a, double b, double R);
+/* Maxwell coexistence of the EOS at temperature T. */
+lbm_status lbm_pr_maxwell(double a, double b, double R, double omega, double T,
+                          double* rho_v, double* rho_l, double* p_sat);
+/* sigma solving Eq. integral_coexistence_curve at the Maxwell densities
+ * (secant from -16 G sigma_0 = 2). */
+lbm_status lbm_fit_sigma(double a, double b, double R, double omega, double G, double T,
+                         double* sigma);
+/* Planar surface tension of Eq. surface_tension for kappa = 0 from the
+ * continuum profile of the normal balance. */
+lbm_status lbm_planar_gamma(double a, double b, double R, double omega, double G, double T,
+                            double sigma, double* gamma0);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_PP_H */

@@ -193,7 +193,10 @@ class Sim:
         uy = np.zeros_like(rho) if uy is None else np.asarray(uy, dtype=self.dtype)
         self.f = feq_weights(rho, ux, uy)
         Tin = np.asarray(T, dtype=self.dtype).copy()
-        self.T = self.apply_t_bc(Tin) if self.p.thermal else Tin
+        if self.p.thermal:  # R8: Dirichlet values hold from the start
+            d = self.tkind == DIRICHLET
+            Tin[d] = self.tval[d]
+        self.T = Tin
         self.n = 0
 
     # ----------------------------------------------------------------- pieces

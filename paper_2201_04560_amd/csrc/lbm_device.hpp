@@ -1,0 +1,154 @@
+// Device-side building blocks of the pseudopotential LBM step (gfx950).
+//
+// Everything here is float64 unless a template parameter says otherwise:
+// the Peng-Robinson EOS and the pseudopotential (Eqs. peng-robinson, psi)
+// are always evaluated in float64, also by the float32-storage kernels,
+// because psi differences near the spinodal lose all digits in float32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int kLanes = 64;               // one wavefront per workgroup
+constexpr int kHaloY = 3;                // RK2 energy update reaches 3 rows
+// x halo (columns recomputed on each side of a 64-lane strip): 3 for the
+// same reason, 4 with walls because the wall closure reads psi at x +- 1
+inline int halo_x(int walls) { return walls ? 4 : 3; }
+inline int tile_x(int walls) { return kLanes - 2 * halo_x(walls); }
+constexpr int kNewtonWall = 8;           // Newton steps of the wall closure
+
+enum { T_FREE = 0, T_DIRICHLET = 1, T_ADIABATIC = 2 };
+enum : uint32_t { ERR_RHO = 1u, ERR_RADICAND = 2u, ERR_TEMP = 4u, ERR_NAN = 8u };
+
+// float64 constants of the model, precomputed on the host
+struct Phys {
+  double a, b, R, G, kw, inv_Tc, Tc, inv_b;
+  double sigma, kappa;
+  double s_e, s_z, s_j, s_q;
+  double sig_e, sig_z;       // 12 sigma / (1/s_e - 1/2), 12 sigma / (1/s_z - 1/2)
+  double eta_l, eta_v, rho_l, rho_v, inv_drho;
+  double gy;
+  double cv, lambda_l, lambda_v, dlam;  // dlam = (lambda_l - lambda_v)/(rho_l - rho_v)
+  double t_side_val;
+  double rho_ref;
+};
+
+// per-column boundary tables (device pointers, nx entries each)
+struct Tables {
+  const double* rho_w_b;
+  const double* rho_w_t;
+  const double* tv_b;
+  const double* tv_t;
+  const int32_t* tk_b;
+  const int32_t* tk_t;
+};
+
+// ---------------------------------------------------------------- EOS
+// sqrt(alpha(T)) = 1 + kw (1 - sqrt(T / T_c))
+__device__ __forceinline__ double sqrt_alpha(double T, const Phys& p) {
+  return 1.0 + p.kw * (1.0 - sqrt(T * p.inv_Tc));
+}
+
+__device__ __forceinline__ double p_eos(double rho, double T, const Phys& p) {
+  const double br = p.b * rho;
+  const double sa = sqrt_alpha(T, p);
+  return rho * p.R * T / (1.0 - br) - p.a * (sa * sa) * rho * rho / (1.0 + 2.0 * br - br * br);
+}
+
+__device__ __forceinline__ double dp_drho(double rho, double T, const Phys& p) {
+  const double br = p.b * rho;
+  const double sa = sqrt_alpha(T, p);
+  const double om = 1.0 - br;
+  const double D = 1.0 + 2.0 * br - br * br;
+  return p.R * T / (om * om) - p.a * (sa * sa) * 2.0 * rho * (1.0 + br) / (D * D);
+}
+
+// (dp/dT)_rho of Eq. energy-equation
+__device__ __forceinline__ double dp_dT(double rho, double T, const Phys& p) {
+  const double br = p.b * rho;
+  const double D = 1.0 + 2.0 * br - br * br;
+  return rho * p.R / (1.0 - br) +
+         p.a * rho * rho * p.kw * sqrt_alpha(T, p) / (sqrt(T * p.Tc) * D);
+}
+
+// psi radicand 2 (p - rho/3) / G
+__device__ __forceinline__ double psi_radicand(double rho, double T, const Phys& p) {
+  return 2.0 * (p_eos(rho, T, p) - rho / 3.0) / p.G;
+}
+
+// pseudopotential with the domain checks of the method; bits go to err
+__device__ __forceinline__ double psi_checked(double rho, double T, const Phys& p, uint32_t& err) {
+  const double rad = psi_radicand(rho, T, p);
+  if (!(rho > 0.0) || !(rho < p.inv_b)) err |= ERR_RHO;
+  if (!(T > 0.0)) err |= ERR_TEMP;
+  if (!(rad > 0.0)) err |= ERR_RADICAND;
+  return sqrt(rad);
+}
+
+__device__ __forceinline__ double dpsi_drho(double rho, double T, double psi, const Phys& p) {
+  return (dp_drho(rho, T, p) - 1.0 / 3.0) / (p.G * psi);
+}
+
+// ----------------------------------------------------------- wall closure
+// Zou-He at a wet wall node with prescribed momentum -F^m/2: the wall
+// density solves rho + sgn psi(rho) B / 2 = K (sgn = +1 bottom, -1 top),
+// where F^m_y = psi(rho) B.  Fixed number of Newton steps from rho = K.
+__device__ __forceinline__ double wall_coef_B(double nb_c, double nb_p, double nb_m, double psi_w,
+                                              double sgn, const Phys& p) {
+  const double nbsum = nb_c / 3.0 + (nb_p + nb_m) / 12.0;
+  return -p.G * sgn * (nbsum - 0.5 * psi_w);
+}
+
+__device__ __forceinline__ double wall_density(double K, double B, double T, double sgn,
+                                               const Phys& p) {
+  double r = K;
+#pragma unroll 1
+  for (int it = 0; it < kNewtonWall; ++it) {
+    const double ps = sqrt(psi_radicand(r, T, p));
+    const double g = r + sgn * 0.5 * ps * B - K;
+    const double dg = 1.0 + sgn * 0.5 * dpsi_drho(r, T, ps, p) * B;
+    r = r - g / dg;
+  }
+  return r;
+}
+
+// ------------------------------------------------------------ utilities
+__device__ __forceinline__ int pmod(int a, int n) {
+  int r = a % n;
+  return r < 0 ? r + n : r;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kLanes);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kLanes));
+  return v;
+}
+
+// temperature boundary kind of node (y, x): side columns, then top, then bottom
+__device__ __forceinline__ int t_kind(int y, int x, int nx, int ny, int side_dir, const Tables& t,
+                                      double& val, const Phys& p) {
+  if (side_dir && (x == 0 || x == nx - 1)) {
+    val = p.t_side_val;
+    return T_DIRICHLET;
+  }
+  if (y == ny - 1) {
+    val = t.tv_t[x];
+    return t.tk_t[x];
+  }
+  if (y == 0) {
+    val = t.tv_b[x];
+    return t.tk_b[x];
+  }
+  val = 0.0;
+  return T_FREE;
+}
+
+}  // namespace lbm

@@ -1,0 +1,112 @@
+// Host-side interface to the device kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_device.hpp"
+
+namespace lbm {
+
+constexpr int kNormSlots = 9;
+
+struct LaunchStep {
+  int fp32;
+  const void* fin;
+  void* fout;
+  const void* Tin;
+  void* Tout;
+  Tables tab;
+  const double* part_in;
+  int npart_in;
+  const double* wall_in;
+  int nwall_in;
+  double* part_out;
+  uint32_t* err;
+  int nx, ny, pitch;
+  long long plane;
+  int ty, ntx, nty, halo;
+  int walls, update_T, side_dir, want_mass, xcd_remap;
+  Phys ph;
+  double* o_rho;
+  double* o_ux;
+  double* o_uy;
+  double* o_T;
+  double* o_f;
+  int f_first, f_count;
+};
+
+template <class S>
+struct InitArgs {
+  S* f;
+  S* Tout;
+  const double* rho;
+  const double* ux;
+  const double* uy;
+  const double* T;
+  double* part_out;
+  Tables tab;
+  Phys ph;
+  int nx, ny, pitch;
+  long long plane;
+  int walls, thermal, side_dir;
+  double rho_ref;
+};
+
+struct LaunchInit {
+  int fp32;
+  void* f;
+  void* Tout;
+  const double* rho;
+  const double* ux;
+  const double* uy;
+  const double* T;
+  double* part_out;
+  Tables tab;
+  Phys ph;
+  int nx, ny, pitch;
+  long long plane;
+  int walls, thermal, side_dir;
+};
+
+template <class S>
+struct WallArgs {
+  const S* fin;
+  const S* Tin;
+  double* wall_out;
+  Tables tab;
+  Phys ph;
+  int nx, ny, pitch;
+  long long plane;
+};
+
+struct LaunchWall {
+  int fp32;
+  const void* fin;
+  const void* Tin;
+  double* wall_out;
+  Tables tab;
+  Phys ph;
+  int nx, ny, pitch;
+  long long plane;
+};
+
+struct NormArgs {
+  const double* rho;
+  const double* ux;
+  const double* uy;
+  const double* T;
+  double* part;
+  int nx, ny, walls;
+  double lambda_l, lambda_v, rho_l, rho_v;
+};
+
+hipError_t launch_step(const LaunchStep& L, hipStream_t st);
+hipError_t launch_macro(const LaunchStep& L, hipStream_t st);
+hipError_t launch_init(const LaunchInit& L, hipStream_t st);
+hipError_t launch_wall_mass(const LaunchWall& L, hipStream_t st);
+hipError_t launch_norms(const NormArgs& a, int nblocks, hipStream_t st);
+int init_blocks(int nx, int ny);
+int wall_blocks(int nx);
+
+}  // namespace lbm

@@ -1,0 +1,172 @@
+"""Python front end of the HIP library: PyTorch provides the device buffer
+and the stream, the library does all the work."""
+import ctypes
+
+import numpy as np
+
+from . import _native as nat
+from ._native import LbmNorms, LbmParams, check, lib
+
+
+def make_params(nx, ny, **kw):
+    """LbmParams with the library defaults, overridden by keyword fields."""
+    p = LbmParams()
+    lib().lbm_default_params(ctypes.byref(p), nx, ny)
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(f"unknown parameter {k}")
+        setattr(p, k, v)
+    return p
+
+
+def buffer_bytes(p):
+    n = ctypes.c_size_t()
+    check(lib().lbm_buffer_bytes(ctypes.byref(p), ctypes.byref(n)), None, "lbm_buffer_bytes")
+    return n.value
+
+
+def _dptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a, shape):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+class Lattice:
+    """One lattice on one GPU (the current torch device)."""
+
+    def __init__(self, params, device=None, stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("a ROCm GPU is required (torch.cuda.is_available() is False)")
+        self.p = params
+        self.nx, self.ny = params.nx, params.ny
+        dev = torch.device("cuda") if device is None else torch.device(device)
+        nbytes = buffer_bytes(params)
+        self._buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        base = self._buf.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self._stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self._ctx = ctypes.c_void_p()
+        check(lib().lbm_create(ctypes.byref(params), ctypes.c_void_p(aligned), nbytes,
+                               ctypes.c_void_p(self._stream.cuda_stream), ctypes.byref(self._ctx)),
+              None, "lbm_create")
+
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            lib().lbm_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ API
+    def set_boundary(self, rho_w_bottom=None, rho_w_top=None, t_bottom_kind=None, t_bottom_val=None,
+                     t_top_kind=None, t_top_val=None):
+        nx = self.nx
+
+        def col(v, dt):
+            if v is None:
+                return None
+            v = np.asarray(v, dtype=dt)
+            return np.ascontiguousarray(np.full(nx, v, dtype=dt) if v.ndim == 0 else v)
+
+        arrs = [col(rho_w_bottom, np.float64), col(rho_w_top, np.float64),
+                col(t_bottom_kind, np.int32), col(t_bottom_val, np.float64),
+                col(t_top_kind, np.int32), col(t_top_val, np.float64)]
+        self._keep = arrs
+        ptrs = []
+        for a in arrs:
+            if a is None:
+                ptrs.append(None)
+            elif a.dtype == np.int32:
+                ptrs.append(a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+            else:
+                ptrs.append(_dptr(a))
+        check(lib().lbm_set_boundary(self._ctx, *ptrs), self._ctx, "lbm_set_boundary")
+
+    def init_fields(self, rho, ux=None, uy=None, T=None):
+        shp = (self.ny, self.nx)
+        rho, ux, uy, T = _f64(rho, shp), _f64(ux, shp), _f64(uy, shp), _f64(T, shp)
+        check(lib().lbm_init_fields(self._ctx, _dptr(rho), _dptr(ux), _dptr(uy), _dptr(T)),
+              self._ctx, "lbm_init_fields")
+
+    def step(self, n=1):
+        check(lib().lbm_step(self._ctx, int(n)), self._ctx, "lbm_step")
+
+    def sync(self):
+        check(lib().lbm_sync(self._ctx), self._ctx, "lbm_sync")
+
+    def fields(self):
+        shp = (self.ny, self.nx)
+        out = [np.empty(shp) for _ in range(4)]
+        check(lib().lbm_read_fields(self._ctx, *[_dptr(a) for a in out]), self._ctx,
+              "lbm_read_fields")
+        return tuple(out)
+
+    def populations(self):
+        f = np.empty((9, self.ny, self.nx))
+        check(lib().lbm_read_populations(self._ctx, _dptr(f)), self._ctx, "lbm_read_populations")
+        return f
+
+    def norms(self):
+        n = LbmNorms()
+        check(lib().lbm_norms(self._ctx, ctypes.byref(n)), self._ctx, "lbm_norms")
+        return {k: getattr(n, k) for k, _ in LbmNorms._fields_}
+
+    @property
+    def step_count(self):
+        return lib().lbm_step_count(self._ctx)
+
+    def last_step_ms(self):
+        v = ctypes.c_double()
+        check(lib().lbm_last_step_time(self._ctx, ctypes.byref(v)), self._ctx, "lbm_last_step_time")
+        return v.value
+
+    def save_state(self):
+        n = ctypes.c_size_t()
+        check(lib().lbm_state_bytes(self._ctx, ctypes.byref(n)), self._ctx, "lbm_state_bytes")
+        buf = np.empty(n.value, dtype=np.uint8)
+        check(lib().lbm_save_state(self._ctx, buf.ctypes.data_as(ctypes.c_void_p), n.value),
+              self._ctx, "lbm_save_state")
+        return buf
+
+    def load_state(self, buf):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        check(lib().lbm_load_state(self._ctx, buf.ctypes.data_as(ctypes.c_void_p), buf.size),
+              self._ctx, "lbm_load_state")
+
+
+# ------------------------------------------------------------ host helpers
+def pr_critical_temperature(a, b=2.0 / 21.0, R=1.0):
+    return lib().lbm_pr_critical_temperature(a, b, R)
+
+
+def pr_maxwell(a, T, b=2.0 / 21.0, R=1.0, omega=0.344):
+    rv, rl, ps = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    check(lib().lbm_pr_maxwell(a, b, R, omega, T, ctypes.byref(rv), ctypes.byref(rl),
+                               ctypes.byref(ps)), None, "lbm_pr_maxwell")
+    return rv.value, rl.value, ps.value
+
+
+def fit_sigma(a, T, b=2.0 / 21.0, R=1.0, omega=0.344, G=-1.0):
+    s = ctypes.c_double()
+    check(lib().lbm_fit_sigma(a, b, R, omega, G, T, ctypes.byref(s)), None, "lbm_fit_sigma")
+    return s.value
+
+
+def planar_gamma(a, T, sigma, b=2.0 / 21.0, R=1.0, omega=0.344, G=-1.0):
+    g = ctypes.c_double()
+    check(lib().lbm_planar_gamma(a, b, R, omega, G, T, sigma, ctypes.byref(g)), None,
+          "lbm_planar_gamma")
+    return g.value

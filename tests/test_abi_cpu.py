@@ -1,0 +1,115 @@
+"""CPU-only checks of the C-ABI library: it loads, exports every symbol of
+include/lbm_pp.h, validates parameters and runs the host parameter
+pipeline (compared with the independent oracle).  No GPU calls."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import thermo as th
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm_pp.h")
+
+
+def header_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2201_04560_amd import _native
+
+    return _native.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2201_04560_amd import _native
+
+    names = header_functions()
+    assert len(names) >= 20
+    bound = {n for n, _, _ in _native.SIGNATURES}
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in bound, f"{n} declared but not bound in Python"
+
+
+def test_struct_sizes_match_header_layout(lib):
+    from paper_2201_04560_amd._native import LbmNorms, LbmParams
+
+    # 8 int32 + 22 double + 8 int32 + 8 double
+    assert ctypes.sizeof(LbmParams) == 8 * 4 + 22 * 8 + 8 * 4 + 8 * 8
+    assert ctypes.sizeof(LbmNorms) == 10 * 8 + 2 * 8
+
+
+def test_validation(lib):
+    from paper_2201_04560_amd import make_params
+    from paper_2201_04560_amd._native import LBM_E_INVAL, LBM_OK
+
+    ok = make_params(16, 16)
+    assert lib.lbm_validate(ctypes.byref(ok)) == LBM_OK
+    bad = [dict(nx=0), dict(ny=0), dict(a=0.0), dict(b=-1.0), dict(s_e=2.0), dict(s_q=0.0),
+           dict(precision=7), dict(walls=1, ny=2), dict(thermal=1, cv=0.0), dict(tile_y=1),
+           dict(rho_l=1.0, rho_v=1.0), dict(G=1.0), dict(n_iso=-1)]
+    for kw in bad:
+        nx = kw.pop("nx", 16)
+        ny = kw.pop("ny", 16)
+        p = make_params(nx, ny, **kw)
+        assert lib.lbm_validate(ctypes.byref(p)) == LBM_E_INVAL, kw
+        n = ctypes.c_size_t()
+        assert lib.lbm_buffer_bytes(ctypes.byref(p), ctypes.byref(n)) == LBM_E_INVAL
+    assert lib.lbm_validate(None) == LBM_E_INVAL
+
+
+def test_buffer_bytes_cover_state(lib):
+    from paper_2201_04560_amd import buffer_bytes, make_params
+
+    for prec, elem in ((0, 8), (1, 4)):
+        p = make_params(300, 200, precision=prec)
+        n = buffer_bytes(p)
+        assert n >= (2 * 9 + 2) * 300 * 200 * elem
+        assert n < 1.5 * (2 * 9 + 2) * 320 * 200 * elem + (1 << 20)
+
+
+def test_create_rejects_bad_buffers(lib):
+    from paper_2201_04560_amd import make_params
+    from paper_2201_04560_amd._native import LBM_E_INVAL, LBM_E_NOMEM
+
+    p = make_params(16, 16)
+    ctx = ctypes.c_void_p()
+    assert lib.lbm_create(ctypes.byref(p), None, 1 << 20, None, ctypes.byref(ctx)) == LBM_E_INVAL
+    assert lib.lbm_create(ctypes.byref(p), ctypes.c_void_p(256), 16, None,
+                          ctypes.byref(ctx)) == LBM_E_NOMEM
+    assert lib.lbm_create(ctypes.byref(p), ctypes.c_void_p(257), 1 << 30, None,
+                          ctypes.byref(ctx)) == LBM_E_INVAL
+    assert b"aligned" in lib.lbm_last_error(None)
+    assert lib.lbm_status_string(5) == b"state left the EOS / pseudopotential domain"
+
+
+@pytest.mark.parametrize("a", [2.0 / 49.0, 6.12e-2 * (128 / 288) ** 2])
+def test_host_parameter_pipeline_matches_oracle(lib, a):
+    import paper_2201_04560_amd as pp
+
+    eos = th.EOS(a)
+    assert abs(pp.pr_critical_temperature(a) - eos.Tc) < 1e-16
+    T = 0.86 * eos.Tc
+    rv, rl, ps = th.maxwell(eos, T)
+    grv, grl, gps = pp.pr_maxwell(a, T)
+    assert abs(grv - rv) < 1e-12 and abs(grl - rl) < 1e-11 and abs(gps - ps) < 1e-14
+    s = th.fit_sigma(eos, T)
+    assert abs(pp.fit_sigma(a, T) - s) < 1e-10
+    g = th.planar_gamma_continuum(eos, T, s)
+    assert abs(pp.planar_gamma(a, T, s) / g - 1) < 1e-7
+
+
+def test_host_pipeline_rejects_supercritical(lib):
+    import paper_2201_04560_amd as pp
+    from paper_2201_04560_amd import LbmError
+
+    with pytest.raises(LbmError):
+        pp.pr_maxwell(2.0 / 49.0, 1.01 * pp.pr_critical_temperature(2.0 / 49.0))

@@ -1,0 +1,184 @@
+"""Parity of the HIP library with the oracle, through the C-ABI.
+
+FP64 storage must agree with the float64 oracle to rounding: 1e-13 after
+one step on random states, 1e-10 (relative to each field's max) after
+1000 steps of the 128^2 static droplet.  Every case prints its name first
+so that a failing GPU run names it."""
+import numpy as np
+import pytest
+
+import cases
+from oracle.step import Sim
+
+pytestmark = pytest.mark.gpu
+
+
+def _lat(c, **kw):
+    from paper_2201_04560_amd import Lattice
+
+    lat = Lattice(cases.lib_params(c, **kw))
+    cases.lib_boundary(lat, c)
+    return lat
+
+
+def _oracle(c, rho, ux, uy, T):
+    s = Sim(cases.oracle_params(c))
+    s.init_fields(rho, ux, uy, T)
+    return s
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def _compare(lat, s, tol, what=""):
+    r, ux, uy, T = lat.fields()
+    ro, uxo, uyo, To = s.fields()
+    f, fo = lat.populations(), s.populations()
+    umax = max(np.abs(uxo).max(), np.abs(uyo).max(), 1e-300)
+    errs = dict(rho=_rel(r, ro), ux=np.abs(ux - uxo).max() / umax, uy=np.abs(uy - uyo).max() / umax,
+                T=_rel(T, To), f=_rel(f, fo))
+    print(what, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, v in errs.items():
+        assert v <= tol, (what, k, v)
+    return errs
+
+
+@pytest.mark.parametrize("nx,ny,walls,thermal,gy", [
+    (8, 6, False, False, 0.0),
+    (8, 6, False, True, 0.0),
+    (7, 8, True, True, 0.0),
+    (9, 7, True, True, -2e-3),
+    (61, 5, False, True, 0.0),
+])
+def test_one_step_random_state(nx, ny, walls, thermal, gy):
+    print(f"case one_step nx={nx} ny={ny} walls={walls} thermal={thermal} gy={gy}", flush=True)
+    c, rho, ux, uy, T = cases.random_tiny(nx, ny, seed=nx * 100 + ny, walls=walls, thermal=thermal,
+                                          gy=gy)
+    s = _oracle(c, rho, ux, uy, T)
+    lat = _lat(c)
+    lat.init_fields(rho, ux, uy, T)
+    _compare(lat, s, 1e-13, "init")
+    s.step(1)
+    lat.step(1)
+    _compare(lat, s, 1e-12, "step1")
+    s.step(4)
+    lat.step(4)
+    _compare(lat, s, 1e-11, "step5")
+
+
+def test_droplet128_1000_steps_fp64():
+    print("case droplet128 fp64 1000 steps", flush=True)
+    c, rho, T = cases.droplet128()
+    s = _oracle(c, rho, None, None, T)
+    lat = _lat(c)
+    lat.init_fields(rho, None, None, T)
+    s.step(1000)
+    lat.step(1000)
+    _compare(lat, s, 1e-10, "droplet128@1000")
+
+
+@pytest.mark.parametrize("tile_y", [2, 5, 16])
+def test_multi_tile_ragged_thermal_ring(tile_y):
+    """150 x 70: three 58-wide tiles with a ragged tail, several row
+    segments, Dirichlet ring as in the vaporisation workload."""
+    print(f"case ring150x70 tile_y={tile_y}", flush=True)
+    eos, Tsat, rv, rl = cases.coexistence()
+    Tout = 0.95 * eos.Tc
+    nx, ny = 150, 70
+    c = dict(nx=nx, ny=ny, a=2.0 / 49.0, sigma=0.1, kappa=0.1, rho_l=rl, rho_v=rv, thermal=True,
+             cv=6.0, lambda_l=2 / 3, lambda_v=2 / 3, t_side_dirichlet=True, t_side_val=Tout,
+             t_bottom_kind=np.full(nx, 1), t_bottom_val=np.full(nx, Tout),
+             t_top_kind=np.full(nx, 1), t_top_val=np.full(nx, Tout), **cases.wl.DROPLET_RATES)
+    rho, T = cases.wl.droplet(nx, ny, 20.0, 4.6 / 5.0, rl, rv, Tsat, Tout, seed=3)
+    s = _oracle(c, rho, None, None, T)
+    lat = _lat(c, tile_y=tile_y)
+    lat.init_fields(rho, None, None, T)
+    s.step(60)
+    lat.step(60)
+    _compare(lat, s, 1e-11, f"ring tile_y={tile_y}")
+
+
+def test_pool_walls_gravity_heater():
+    """Walls, psi-based wetting with a heater strip, gravity (rho_bar), mixed
+    Dirichlet / adiabatic bottom, Dirichlet top."""
+    print("case pool 80x48", flush=True)
+    eos, Tsat, rv, rl = cases.coexistence()
+    nx, ny = 80, 48
+    kb = np.full(nx, 2)
+    vb = np.full(nx, Tsat)
+    rwb = np.full(nx, 6.5)
+    kb[30:50] = 1
+    vb[30:50] = 0.95 * eos.Tc
+    rwb[30:50] = 3.44
+    c = dict(nx=nx, ny=ny, a=2.0 / 49.0, sigma=0.1103, kappa=0.0, rho_l=rl, rho_v=rv, walls=True,
+             thermal=True, gy=-3e-5, cv=5.0, lambda_l=1.95, lambda_v=0.114, rho_w_bottom=rwb,
+             rho_w_top=0.38, t_bottom_kind=kb, t_bottom_val=vb, t_top_kind=np.full(nx, 1),
+             t_top_val=np.full(nx, Tsat), **cases.wl.POOL_RATES)
+    rho, T = cases.wl.pool(nx, ny, 30.0, 2.3, rl, rv, Tsat, seed_radius=6.0, seed=1)
+    s = _oracle(c, rho, None, None, T)
+    lat = _lat(c, tile_y=8)
+    lat.init_fields(rho, None, None, T)
+    for n in (1, 49, 150):
+        s.step(n)
+        lat.step(n)
+        _compare(lat, s, 1e-10, f"pool step {s.n}")
+
+
+def test_tile_shape_invariance_bitwise():
+    """Without gravity the result does not depend on the tiling or on the
+    XCD remap: identical bits."""
+    print("case tile invariance", flush=True)
+    c, rho, ux, uy, T = cases.random_tiny(130, 40, seed=5, walls=True, thermal=True)
+    outs = []
+    for ty, rm in ((4, 1), (13, 0), (40, 1)):
+        lat = _lat(c, tile_y=ty, xcd_remap=rm)
+        lat.init_fields(rho, ux, uy, T)
+        lat.step(7)
+        outs.append(lat.populations())
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+def test_checkpoint_restart_bitwise():
+    print("case checkpoint", flush=True)
+    c, rho, ux, uy, T = cases.random_tiny(70, 30, seed=9, walls=True, thermal=True, gy=-1e-3)
+    lat = _lat(c, tile_y=8)
+    lat.init_fields(rho, ux, uy, T)
+    lat.step(5)
+    st = lat.save_state()
+    lat.step(6)
+    a = lat.populations()
+    lat.load_state(st)
+    assert lat.step_count == 5
+    lat.step(6)
+    assert np.array_equal(a, lat.populations())
+
+
+def test_domain_error_is_reported():
+    print("case domain error", flush=True)
+    from paper_2201_04560_amd import LbmError
+
+    c, rho, ux, uy, T = cases.random_tiny(16, 16, seed=2)
+    rho[5, 5] = 9.6  # psi radicand < 0 at 0.86 T_c
+    lat = _lat(c)
+    lat.init_fields(rho, ux, uy, T)
+    lat.step(1)
+    with pytest.raises(LbmError) as ei:
+        lat.fields()
+    assert ei.value.status == 5
+
+
+def test_fp32_shifted_tracks_fp64():
+    """FP32 shifted storage: parity unpinned (reported); here only a loose
+    agreement with the oracle on the random walls case after 50 steps."""
+    print("case fp32 shifted", flush=True)
+    c, rho, ux, uy, T = cases.random_tiny(64, 32, seed=4, walls=True, thermal=True, gy=-1e-4)
+    s = _oracle(c, rho, ux, uy, T)
+    lat = _lat(c, precision=1)
+    lat.init_fields(rho, ux, uy, T)
+    s.step(50)
+    lat.step(50)
+    r, ux2, uy2, T2 = lat.fields()
+    ro, _, _, To = s.fields()
+    print("fp32 rho rel", _rel(r, ro), "T rel", _rel(T2, To), flush=True)
+    assert _rel(r, ro) < 1e-4 and _rel(T2, To) < 1e-5
