@@ -1,0 +1,277 @@
+#!/usr/bin/env python3
+"""Throughput of the fused pseudopotential-LBM step on one MI355X.
+
+Workload (the metric's configuration): droplet vaporisation on a 512 x 512
+periodic lattice -- a liquid disk of radius 60 (seed-jittered by +-0.5) at
+T_sat = 0.86 T_c in vapour held at 0.95 T_c on the outer ring, Peng-Robinson
+EOS a = 2/49, b = 2/21, sigma = kappa = 0.1, all MRT rates 1.25, c_v = 6,
+lambda = 2/3, no gravity, energy equation on from step 0.  The float32
+shifted-storage step is timed, then the float64 plain step on the same
+input; both run warmup + steps time steps and the final rho / T of the
+float32 run are compared with the float64 run.
+
+Prints ONE JSON line (last line of stdout) with the metric, the roofline
+of the step kernel (HIP events around every launch in the timed region),
+the float64 comparison, an HBM-sized run (4096 x 4096 pool boiling
+physics: walls, heater, gravity) and the float64 oracle timed on the host
+(one core, a bounded number of steps of the same workload).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2201_04560_amd", "csrc", "lbm_step.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def alg_bytes_per_node(fp32, thermal=True):
+    """Populations in and out (9 + 9) and T in and out: 80 B (float32) /
+    160 B (float64) per lattice update."""
+    e = 4 if fp32 else 8
+    return (18 + (2 if thermal else 0)) * e
+
+
+def vaporisation_case(n=512, seed=0):
+    import paper_2201_04560_amd as pp
+    import workloads as wl
+
+    a = 2.0 / 49.0
+    Tc = pp.pr_critical_temperature(a)
+    Tsat, Tout = 0.86 * Tc, 0.95 * Tc
+    rv, rl, _ = pp.pr_maxwell(a, Tsat)
+    rho, T = wl.droplet(n, n, 60.0 * n / 512, 4.6 / 5.0, rl, rv, Tsat, Tout, seed=seed)
+    kw = dict(a=a, sigma=0.1, kappa=0.1, rho_l=rl, rho_v=rv, thermal=1, cv=6.0,
+              lambda_l=2.0 / 3.0, lambda_v=2.0 / 3.0, t_side_dirichlet=1, t_side_val=Tout, rho_ref=rv)
+    kw.update({k: v for k, v in wl.DROPLET_RATES.items()})
+    bnd = dict(t_bottom_kind=1, t_bottom_val=Tout, t_top_kind=1, t_top_val=Tout)
+    return n, n, kw, bnd, rho, T
+
+
+def pool_case(nx=4096, ny=4096):
+    import paper_2201_04560_amd as pp
+    import workloads as wl
+
+    a = 2.0 / 49.0
+    Tc = pp.pr_critical_temperature(a)
+    Tsat = 0.86 * Tc
+    rv, rl, _ = pp.pr_maxwell(a, Tsat)
+    rho, T = wl.pool(nx, ny, ny * 1400.0 / 2048.0, 2.3, rl, rv, Tsat, seed_radius=8.0, seed=0)
+    kw = dict(a=a, sigma=pp.fit_sigma(a, Tsat), kappa=0.0, rho_l=rl, rho_v=rv, walls=1, thermal=1,
+              gy=-3e-5, cv=5.0, lambda_l=1.95, lambda_v=0.114, rho_ref=rv)
+    kw.update({k: v for k, v in wl.POOL_RATES.items()})
+    h0, h1 = nx // 2 - nx // 16, nx // 2 + nx // 16
+    kb = np.full(nx, 2, np.int32)
+    kb[h0:h1] = 1
+    vb = np.full(nx, Tsat)
+    vb[h0:h1] = 0.95 * Tc
+    rwb = np.full(nx, 6.50)
+    rwb[h0:h1] = 3.44
+    bnd = dict(rho_w_bottom=rwb, rho_w_top=0.38, t_bottom_kind=kb, t_bottom_val=vb, t_top_kind=1,
+               t_top_val=Tsat)
+    return nx, ny, kw, bnd, rho, T
+
+
+def run_lattice(case, precision, warmup, steps, want_fields=True, tile_y=0):
+    import torch
+
+    from paper_2201_04560_amd import Lattice, make_params
+
+    nx, ny, kw, bnd, rho, T = case
+    lat = Lattice(make_params(nx, ny, precision=precision, tile_y=tile_y, **kw))
+    lat.set_boundary(**bnd)
+    lat.init_fields(rho, None, None, T)
+    if warmup:
+        lat.step(warmup)
+    lat.sync()
+    torch.cuda.synchronize()
+    lat.kernel_timing(True)
+    t0 = time.perf_counter()
+    lat.step(steps)
+    lat.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ksum, kcnt = lat.kernel_times()
+    lat.kernel_timing(False)
+    out = dict(wall_s=t1 - t0, ev_ms=lat.last_step_ms(), kernel_ms_avg=ksum / max(kcnt, 1),
+               launches=kcnt)
+    if want_fields:
+        out["fields"] = lat.fields()
+        out["norms"] = lat.norms()
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    return out
+
+
+def roofline(fp32, nodes, kernel_ms, traffic):
+    b = alg_bytes_per_node(fp32) * nodes
+    achieved = b / (kernel_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "alg_bytes_per_launch": b, "kernel_ms_avg": round(kernel_ms, 5)}
+
+
+def measured_traffic(key):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, valid
+    only while the kernel source is the one they were taken on."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+        h = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        if t.get("kernel_sha256") != h:
+            return None
+        return t.get("per_launch_bytes", {}).get(key)
+    except (OSError, ValueError):
+        return None
+
+
+def cpu_baseline(case, budget_s=15.0):
+    """The float64 oracle on the host, one core, a bounded number of steps."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:
+        threadpool_limits = None
+    from oracle.step import Params, Sim
+
+    nx, ny, kw, bnd, rho, T = case
+    keys = ["a", "sigma", "kappa", "rho_l", "rho_v", "thermal", "cv", "lambda_l", "lambda_v",
+            "t_side_val", "s_rho", "s_e", "s_zeta", "s_j", "s_q"]
+    p = Params(nx=nx, ny=ny, t_side_dirichlet=True, t_bottom_kind=bnd["t_bottom_kind"],
+               t_bottom_val=bnd["t_bottom_val"], t_top_kind=bnd["t_top_kind"],
+               t_top_val=bnd["t_top_val"], **{k: kw[k] for k in keys})
+    import contextlib
+
+    lim = threadpool_limits(limits=1) if threadpool_limits else contextlib.nullcontext()
+    with lim:
+        s = Sim(p)
+        s.init_fields(rho, None, None, T)
+        t0 = time.perf_counter()
+        s.step(2)
+        per = (time.perf_counter() - t0) / 2
+        n = max(3, int(budget_s / per))
+        t0 = time.perf_counter()
+        s.step(n)
+        dt = time.perf_counter() - t0
+    return {"value": round(nx * ny * n / dt / 1e6, 4), "unit": "MLUPS", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{nx}x{ny} droplet vaporisation, {n} float64 oracle steps after 2 untimed, "
+                      f"{dt:.1f} s on one host core (BLAS threads limited to 1)"}
+
+
+def rel_err(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--sizing-steps", type=int, default=200)
+    ap.add_argument("--no-sizing", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["fp32", "fp64", "both"], default="both")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "a multi-GPU slab decomposition is described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    from paper_2201_04560_amd import LBM_FP32_SHIFTED, LBM_FP64
+
+    case = vaporisation_case()
+    nx, ny = case[0], case[1]
+    nodes = nx * ny
+    res = {}
+    for name, prec in (("fp32", LBM_FP32_SHIFTED), ("fp64", LBM_FP64)):
+        if args.only not in (name, "both"):
+            continue
+        log(f"bench: {name} {nx}x{ny} vaporisation, warmup {args.warmup}, steps {args.steps}")
+        res[name] = run_lattice(case, prec, args.warmup, args.steps)
+        r = res[name]
+        log(f"bench: {name} {args.steps * nodes / r['wall_s'] / 1e6:.0f} MLUPS, kernel "
+            f"{r['kernel_ms_avg'] * 1e3:.2f} us avg over {r['launches']} launches")
+
+    main_name = "fp32" if "fp32" in res else "fp64"
+    m = res[main_name]
+    value = args.steps * nodes / m["wall_s"] / 1e6
+    out = {
+        "metric": "MLUPS + % HBM roofline, FP32 fused vs FP64 plain step, at stated rho/T error",
+        "value": round(value, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(m["wall_s"] * 1e3 / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if main_name == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "droplet vaporisation 512x512, PR a=2/49 b=2/21, r=60 at 0.86 Tc "
+                               "in vapour held at 0.95 Tc, sigma=kappa=0.1, cv=6, lambda=2/3, no "
+                               "gravity, seed 0 (+-0.5 interface jitter)",
+                   "nx": nx, "ny": ny, "storage": "f32 shifted populations (f - w rho_v) + f32 T; "
+                   "f64 EOS/psi/forces and reductions", "steps_total": args.warmup + args.steps},
+        "roofline": roofline(main_name == "fp32", nodes, m["kernel_ms_avg"],
+                             measured_traffic(f"vaporisation512_{main_name}")),
+    }
+    if "fp32" in res and "fp64" in res:
+        f32, f64 = res["fp32"], res["fp64"]
+        r32, _, _, T32 = f32["fields"]
+        r64, _, _, T64 = f64["fields"]
+        out["fp64_plain"] = {
+            "value": round(args.steps * nodes / f64["wall_s"] / 1e6, 1), "unit": "MLUPS",
+            "ms_per_step": round(f64["wall_s"] * 1e3 / args.steps, 5),
+            "roofline": roofline(False, nodes, f64["kernel_ms_avg"],
+                                 measured_traffic("vaporisation512_fp64")),
+        }
+        out["speedup_fp32_vs_fp64"] = round(f64["wall_s"] / f32["wall_s"], 3)
+        out["fp32_error_vs_fp64"] = {
+            "after_steps": args.warmup + args.steps,
+            "rho_max_rel": rel_err(r32, r64), "T_max_rel": rel_err(T32, T64),
+            "mass_rel": abs(f32["norms"]["mass"] / f64["norms"]["mass"] - 1),
+            "liquid_fraction_fp32": float((r32 > 0.5 * (case[2]["rho_l"] + case[2]["rho_v"])).mean()),
+            "liquid_fraction_fp64": float((r64 > 0.5 * (case[2]["rho_l"] + case[2]["rho_v"])).mean()),
+        }
+    if not args.no_sizing:
+        pc = pool_case()
+        sz = {}
+        for name, prec in (("fp32", LBM_FP32_SHIFTED), ("fp64", LBM_FP64)):
+            if args.only not in (name, "both"):
+                continue
+            log(f"bench: sizing {name} {pc[0]}x{pc[1]} pool, {args.sizing_steps} steps")
+            r = run_lattice(pc, prec, 20, args.sizing_steps, want_fields=False)
+            n2 = pc[0] * pc[1]
+            sz[name] = {"value": round(args.sizing_steps * n2 / r["wall_s"] / 1e6, 1),
+                        "unit": "MLUPS",
+                        "roofline": roofline(name == "fp32", n2, r["kernel_ms_avg"],
+                                             measured_traffic(f"pool4096_{name}"))}
+        out["hbm_sized_run"] = {"workload": "pool boiling physics 4096x4096 (walls, heater, "
+                                            "gravity, thermal), 1.3 GB f32 / 2.7 GB f64 state",
+                                **sz}
+    if not args.no_cpu_baseline:
+        log("bench: cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(case)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -157,6 +157,13 @@ int64_t lbm_step_count(const lbm_ctx* ctx);
  * events recorded on the context stream around its launches.  Waits for the
  * second event. */
 lbm_status lbm_last_step_time(lbm_ctx* ctx, double* total_ms);
+/* Per-launch timing of the step kernel: while enabled, every step-kernel
+ * launch of lbm_step() is bracketed by a pair of HIP events on the context
+ * stream (the event pool grows on the host as needed).  lbm_kernel_times()
+ * waits for the recorded events, returns the sum of the kernel spans (ms)
+ * and their number, and clears the record.  Enabling also clears it. */
+lbm_status lbm_kernel_timing(lbm_ctx* ctx, int32_t enable);
+lbm_status lbm_kernel_times(lbm_ctx* ctx, double* sum_ms, int64_t* count);
 
 /* ---- host parameter pipeline (Sec. 3); float64, no GPU ----------------- */
 /* T_c of Eq. peng-robinson's a = 0.45724 R^2 T_c^2/p_c, b = 0.0778 R T_c/p_c */

@@ -61,6 +61,8 @@ SIGNATURES = [
     ("lbm_sync", c_int32, [c_void_p]),
     ("lbm_step_count", c_int64, [c_void_p]),
     ("lbm_last_step_time", c_int32, [c_void_p, _DP]),
+    ("lbm_kernel_timing", c_int32, [c_void_p, c_int32]),
+    ("lbm_kernel_times", c_int32, [c_void_p, _DP, P(c_int64)]),
     ("lbm_pr_critical_temperature", c_double, [c_double, c_double, c_double]),
     ("lbm_pr_maxwell", c_int32, [c_double, c_double, c_double, c_double, c_double, _DP, _DP, _DP]),
     ("lbm_fit_sigma", c_int32, [c_double, c_double, c_double, c_double, c_double, c_double, _DP]),

@@ -123,6 +123,10 @@ struct lbm_ctx {
   std::string err;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool timed = false;
+  // optional per-launch timing of the step kernel (event pairs on the stream)
+  bool ktime = false;
+  std::vector<hipEvent_t> kev;
+  size_t kused = 0;
 
   void* f(int i) const { return base + L.off_f[i]; }
   void* T(int i) const { return base + L.off_T[i]; }
@@ -279,6 +283,7 @@ void lbm_destroy(lbm_ctx* c) {
   if (!c) return;
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  for (hipEvent_t e : c->kev) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -449,7 +454,21 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
       HIP_TRY(c, launch_wall_mass(W, c->stream));
       L.nwall_in = wall_blocks(c->p.nx);
     }
+    if (c->ktime) {
+      if (c->kused + 2 > c->kev.size()) {
+        for (int j = 0; j < 2; ++j) {
+          hipEvent_t e;
+          HIP_TRY(c, hipEventCreate(&e));
+          c->kev.push_back(e);
+        }
+      }
+      HIP_TRY(c, hipEventRecord(c->kev[c->kused], c->stream));
+    }
     HIP_TRY(c, launch_step(L, c->stream));
+    if (c->ktime) {
+      HIP_TRY(c, hipEventRecord(c->kev[c->kused + 1], c->stream));
+      c->kused += 2;
+    }
     c->cur ^= 1;
     if (L.update_T) c->Tcur ^= 1;
     if (grav) {
@@ -460,6 +479,28 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
   }
   HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
   c->timed = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_kernel_timing(lbm_ctx* c, int32_t enable) {
+  if (!c) return LBM_E_INVAL;
+  c->ktime = enable != 0;
+  c->kused = 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_kernel_times(lbm_ctx* c, double* sum_ms, int64_t* count) {
+  if (!c || !sum_ms || !count) return LBM_E_INVAL;
+  double s = 0.0;
+  for (size_t i = 0; i + 1 < c->kused; i += 2) {
+    HIP_TRY(c, hipEventSynchronize(c->kev[i + 1]));
+    float ms = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, c->kev[i], c->kev[i + 1]));
+    s += ms;
+  }
+  *sum_ms = s;
+  *count = int64_t(c->kused / 2);
+  c->kused = 0;
   return LBM_OK;
 }
 

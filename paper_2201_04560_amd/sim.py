@@ -133,6 +133,16 @@ class Lattice:
         check(lib().lbm_last_step_time(self._ctx, ctypes.byref(v)), self._ctx, "lbm_last_step_time")
         return v.value
 
+    def kernel_timing(self, enable=True):
+        check(lib().lbm_kernel_timing(self._ctx, int(bool(enable))), self._ctx, "lbm_kernel_timing")
+
+    def kernel_times(self):
+        """(sum of step-kernel spans in ms, number of launches) since enabling."""
+        s, n = ctypes.c_double(), ctypes.c_int64()
+        check(lib().lbm_kernel_times(self._ctx, ctypes.byref(s), ctypes.byref(n)), self._ctx,
+              "lbm_kernel_times")
+        return s.value, n.value
+
     def save_state(self):
         n = ctypes.c_size_t()
         check(lib().lbm_state_bytes(self._ctx, ctypes.byref(n)), self._ctx, "lbm_state_bytes")
