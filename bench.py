@@ -184,6 +184,11 @@ def main():
     ap.add_argument("--no-sizing", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fp32", "fp64", "both"], default="both")
+    ap.add_argument("--profile-case", choices=["vaporisation512", "pool4096"], default=None,
+                    help="profiling run: only this case (precision from --only), --steps steps, "
+                         "plus a device copy of --copy-mib MiB (counter calibration); no JSON")
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--tile-y", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -196,6 +201,24 @@ def main():
     torch.cuda.set_device(0)
     from paper_2201_04560_amd import LBM_FP32_SHIFTED, LBM_FP64
 
+    if args.profile_case:
+        pcase = vaporisation_case() if args.profile_case == "vaporisation512" else pool_case()
+        for name, prec in (("fp32", LBM_FP32_SHIFTED), ("fp64", LBM_FP64)):
+            if args.only in (name, "both"):
+                r = run_lattice(pcase, prec, args.warmup, args.steps, want_fields=False,
+                                tile_y=args.tile_y)
+                log(f"profile: {args.profile_case} {name} kernel {r['kernel_ms_avg'] * 1e3:.2f} us "
+                    f"avg over {r['launches']} launches")
+        if args.copy_mib > 0:
+            n = args.copy_mib * (1 << 20) // 4
+            src = torch.ones(n, dtype=torch.float32, device="cuda")
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            log(f"profile: copy kernel {args.copy_mib} MiB read + {args.copy_mib} MiB written, 3 times")
+        return
+
     case = vaporisation_case()
     nx, ny = case[0], case[1]
     nodes = nx * ny
@@ -204,7 +227,7 @@ def main():
         if args.only not in (name, "both"):
             continue
         log(f"bench: {name} {nx}x{ny} vaporisation, warmup {args.warmup}, steps {args.steps}")
-        res[name] = run_lattice(case, prec, args.warmup, args.steps)
+        res[name] = run_lattice(case, prec, args.warmup, args.steps, tile_y=args.tile_y)
         r = res[name]
         log(f"bench: {name} {args.steps * nodes / r['wall_s'] / 1e6:.0f} MLUPS, kernel "
             f"{r['kernel_ms_avg'] * 1e3:.2f} us avg over {r['launches']} launches")

@@ -24,7 +24,7 @@ enum : uint32_t { ERR_RHO = 1u, ERR_RADICAND = 2u, ERR_TEMP = 4u, ERR_NAN = 8u }
 
 // float64 constants of the model, precomputed on the host
 struct Phys {
-  double a, b, R, G, kw, inv_Tc, Tc, inv_b;
+  double a, b, R, G, kw, inv_Tc, Tc, inv_b, inv_sqrtTc, akw_isTc;  // akw_isTc = a kw / sqrt(T_c)
   double sigma, kappa;
   double s_e, s_z, s_j, s_q;
   double sig_e, sig_z;       // 12 sigma / (1/s_e - 1/2), 12 sigma / (1/s_z - 1/2)
@@ -33,6 +33,17 @@ struct Phys {
   double cv, lambda_l, lambda_v, dlam;  // dlam = (lambda_l - lambda_v)/(rho_l - rho_v)
   double t_side_val;
   double rho_ref;
+};
+
+// constants of the collision and the energy update in the compute type C
+template <class C>
+struct PhysC {
+  C s_e, s_z, s_q;
+  C snu_const;             // used when eta_l == eta_v
+  C eta_l, eta_v, rho_v, inv_drho;
+  C lambda_v, dlam, inv_cv;
+  C kw, inv_sqrtTc, akw_isTc;
+  int snu_varies;
 };
 
 // per-column boundary tables (device pointers, nx entries each)
@@ -89,6 +100,60 @@ __device__ __forceinline__ double psi_checked(double rho, double T, const Phys& 
 
 __device__ __forceinline__ double dpsi_drho(double rho, double T, double psi, const Phys& p) {
   return (dp_drho(rho, T, p) - 1.0 / 3.0) / (p.G * psi);
+}
+
+// ------------------------------------------- fast float64 rcp / rsqrt / sqrt
+// Hardware estimates refined by two Newton steps: ~1 ulp, not correctly
+// rounded (the IEEE expansions cost 2-3x the instructions).
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ double rsq64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  double t = fma(-h * y, y, 0.5);
+  y = fma(y, t, y);
+  t = fma(-h * y, y, 0.5);
+  return fma(y, t, y);
+}
+__device__ __forceinline__ float rsq_c(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsq_c(double x) { return rsq64(x); }
+__device__ __forceinline__ float rcp_c(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_c(double x) { return rcp64(x); }
+
+// EOS terms of one node, shared by psi (stage A) and (dp/dT)_rho (energy
+// stages): A1 = rho R / (1 - b rho), A2 = rho^2 / (1 + 2 b rho - b^2 rho^2),
+// rsqT = 1 / sqrt(T); p = A1 T - a alpha(T) A2.
+struct EosNode {
+  double A1, A2, rsqT, rad;
+};
+__device__ __forceinline__ EosNode eos_node(double rho, double T, const Phys& p) {
+  EosNode e;
+  const double br = p.b * rho;
+  const double om = 1.0 - br;
+  const double D = 1.0 + 2.0 * br - br * br;
+  const double inv = rcp64(om * D);
+  e.A1 = rho * p.R * D * inv;
+  e.A2 = rho * rho * om * inv;
+  e.rsqT = rsq64(T);
+  const double sa = 1.0 + p.kw * (1.0 - T * e.rsqT * p.inv_sqrtTc);
+  const double pr = e.A1 * T - p.a * (sa * sa) * e.A2;
+  e.rad = 2.0 * (pr - rho * (1.0 / 3.0)) / p.G;
+  return e;
+}
+// psi = sqrt(rad) with the domain checks of the method
+__device__ __forceinline__ double psi_fast(double rho, double T, const EosNode& e, const Phys& p,
+                                           uint32_t& err) {
+  if (!(rho > 0.0) || !(rho < p.inv_b)) err |= ERR_RHO;
+  if (!(T > 0.0)) err |= ERR_TEMP;
+  if (!(e.rad > 0.0)) err |= ERR_RADICAND;
+  const double y = rsq64(e.rad);
+  double s = e.rad * y;  // one Newton correction of the root itself
+  return fma(0.5 * y, fma(-s, s, e.rad), s);
 }
 
 // ----------------------------------------------------------- wall closure

@@ -80,6 +80,8 @@ Phys make_phys(const lbm_params& p) {
   h.kw = 0.37464 + 1.54226 * p.omega - 0.2699 * p.omega * p.omega;
   h.Tc = 0.0778 * p.a / (0.45724 * p.b * p.R);
   h.inv_Tc = 1.0 / h.Tc;
+  h.inv_sqrtTc = 1.0 / std::sqrt(h.Tc);
+  h.akw_isTc = p.a * h.kw * h.inv_sqrtTc;
   h.inv_b = 1.0 / p.b;
   h.sigma = p.sigma;
   h.kappa = p.kappa;
