@@ -35,11 +35,14 @@ struct Layout {
 };
 
 int default_tile_y(int nx, int ny, int walls) {
+  // aim at ~8 one-wave workgroups per CU; small lattices get short strips
+  // (the step is then bound by one wave's per-row latency), large ones long
+  // strips (less recomputation of the 6 halo rows)
   const int ntx = (nx + tile_x(walls) - 1) / tile_x(walls);
-  const int target = 4096;  // ~16 resident waves on each of the 256 CUs
+  const int target = 8192;
   const int nty = std::max(1, (target + ntx - 1) / ntx);
   int ty = (ny + nty - 1) / nty;
-  ty = std::max(ty, 8);
+  ty = std::max(ty, 4);
   ty = std::min(ty, 256);
   return std::max(2, std::min(ty, std::max(ny, 2)));
 }
