@@ -171,6 +171,102 @@ def cpu_baseline(case, budget_s=15.0):
                       f"{dt:.1f} s on one host core (BLAS threads limited to 1)"}
 
 
+def ladder_case(k, seed, precision, steps0):
+    """Mesh k of the pool-boiling refinement ladder (128x256 base, dx = 2^-k)
+    with its seeded initial fields: liquid below 1400/2048 of the height,
+    tanh interface and nucleation half-disk scaled with the mesh."""
+    import workloads as wl
+    from paper_2201_04560_amd.ladder import pool_level
+
+    L = pool_level(k, steps0=steps0, precision=precision)
+    lv, nx, ny = L["level"], L["nx"], L["ny"]
+    rho, T = wl.pool(nx, ny, ny * 1400.0 / 2048.0, 2.3 * 2 ** k, lv["rho_l"], lv["rho_v"], lv["T"],
+                     seed_radius=6.0 * 2 ** k, seed=100 * k + seed)
+    return L, rho, T
+
+
+def ladder_bench(steps0, levels=(0, 1, 2, 3), seeds=(0, 1, 2, 3), tile_cache=None):
+    """16 grids (4 meshes x 4 seeds): float32 shifted storage in one batched,
+    graph-replayed launch per step with autotuned strip heights, against the
+    plain float64 step one launch per step per grid; both advance mesh k by
+    steps0 4^k steps (the same physical time)."""
+    import torch
+
+    from paper_2201_04560_amd import Batch, Lattice
+    from paper_2201_04560_amd.ladder import TileCache
+
+    cache = TileCache(tile_cache)
+    dev = torch.cuda.get_device_name(0)
+    specs = [(k, sd) for k in levels for sd in seeds]
+
+    def build(precision):
+        lats, steps = [], []
+        for k, sd in specs:
+            L, rho, T = ladder_case(k, sd, precision, steps0)
+            lat = Lattice(L["params"])
+            lat.set_boundary(**L["boundary"])
+            lat.init_fields(rho, None, None, T)
+            lats.append(lat)
+            steps.append(L["steps"])
+        return lats, steps
+
+    lats32, steps = build(1)
+    tiles = {}
+    for (k, sd), lat in zip(specs, lats32):
+        if k not in tiles:
+            tiles[k] = cache.tune(lat, device=dev)
+        lat.tile_y = tiles[k]
+    log(f"bench: ladder tiles {tiles}, steps {sorted(set(steps))}")
+    b = Batch(lats32)
+    b.run([2] * len(lats32))  # warm-up: graph instantiation path and caches
+    torch.cuda.synchronize()
+    # the warm-up advanced every grid by 2 steps: the fp64 run does the same
+    t0 = time.perf_counter()
+    b.run(steps)
+    torch.cuda.synchronize()
+    t32 = time.perf_counter() - t0
+    ms32, launches, graphs = b.last_time()
+    lats64, _ = build(0)
+    for lat in lats64:
+        lat.step(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for lat, n in zip(lats64, steps):
+        lat.step(n)
+    torch.cuda.synchronize()
+    t64 = time.perf_counter() - t0
+    lu = sum(l.nx * l.ny * n for l, n in zip(lats32, steps))
+    per_level = {}
+    for (k, sd), a, c in zip(specs, lats32, lats64):
+        r32, _, _, T32 = a.fields()
+        r64, _, _, T64 = c.fields()
+        e = per_level.setdefault(k, {"grid": f"{a.nx}x{a.ny}", "steps": steps[specs.index((k, sd))],
+                                     "tile_y": tiles[k], "rho_max_rel": 0.0, "T_max_rel": 0.0,
+                                     "kappa": None})
+        e["rho_max_rel"] = max(e["rho_max_rel"], rel_err(r32, r64))
+        e["T_max_rel"] = max(e["T_max_rel"], rel_err(T32, T64))
+    for k in per_level:
+        from paper_2201_04560_amd.ladder import pool_level
+
+        lv = pool_level(k, steps0=steps0)["level"]
+        per_level[k].update(a=lv["a"], sigma=round(lv["sigma"], 6), kappa=round(lv["kappa"], 6),
+                            gy=lv["gy"])
+    b.close()
+    for lat in lats32 + lats64:
+        lat.close()
+    torch.cuda.empty_cache()
+    return {"grids": len(specs), "lattice_updates": lu,
+            "fp32_batched": {"wall_s": round(t32, 4), "device_ms": round(ms32, 3),
+                             "MLUPS": round(lu / t32 / 1e6, 1), "step_launches": launches,
+                             "graph_launches": graphs},
+            "fp64_plain_per_grid": {"wall_s": round(t64, 4), "MLUPS": round(lu / t64 / 1e6, 1),
+                                    "kernel_launches": sum(steps)},
+            "speedup": round(t64 / t32, 3),
+            "levels": {str(k): v for k, v in per_level.items()},
+            "accuracy": "max relative rho / T difference, float32 batched vs float64 plain, "
+                        "per mesh over its 4 seeds, after the full schedule"}
+
+
 def rel_err(a, b):
     return float(np.abs(a - b).max() / np.abs(b).max())
 
@@ -189,6 +285,10 @@ def main():
                          "plus a device copy of --copy-mib MiB (counter calibration); no JSON")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--tile-y", type=int, default=0)
+    ap.add_argument("--ladder-steps0", type=int, default=50,
+                    help="steps of the coarsest ladder mesh (mesh k runs steps0 * 4^k)")
+    ap.add_argument("--no-ladder", action="store_true")
+    ap.add_argument("--tile-cache", default=None, help="JSON cache of autotuned strip heights")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -290,6 +390,9 @@ def main():
         out["hbm_sized_run"] = {"workload": "pool boiling physics 4096x4096 (walls, heater, "
                                             "gravity, thermal), 1.3 GB f32 / 2.7 GB f64 state",
                                 **sz}
+    if not args.no_ladder:
+        log(f"bench: refinement ladder, steps0 {args.ladder_steps0}")
+        out["ladder"] = ladder_bench(args.ladder_steps0, tile_cache=args.tile_cache)
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(case)

@@ -149,6 +149,12 @@ lbm_status lbm_state_bytes(const lbm_ctx* ctx, size_t* bytes);
 lbm_status lbm_save_state(lbm_ctx* ctx, void* host, size_t bytes);
 lbm_status lbm_load_state(lbm_ctx* ctx, const void* host, size_t bytes);
 
+/* Rows per workgroup strip of the step kernel (>= 2).  The result of a step
+ * does not depend on it (bitwise without gravity; rho_bar's summation order
+ * changes with it otherwise). */
+lbm_status lbm_set_tile_y(lbm_ctx* ctx, int32_t tile_y);
+int32_t lbm_get_tile_y(const lbm_ctx* ctx);
+
 /* Wait for the context stream; report sticky device errors. */
 lbm_status lbm_sync(lbm_ctx* ctx);
 int64_t lbm_step_count(const lbm_ctx* ctx);
@@ -165,6 +171,38 @@ lbm_status lbm_last_step_time(lbm_ctx* ctx, double* total_ms);
 lbm_status lbm_kernel_timing(lbm_ctx* ctx, int32_t enable);
 lbm_status lbm_kernel_times(lbm_ctx* ctx, double* sum_ms, int64_t* count);
 
+/* ---- batches of lattices: the mesh-refinement ladder (Sec. 3) ----------- */
+typedef struct lbm_batch lbm_batch;
+/* Device bytes of the argument tables of a batch (up to 64 lattices and 64
+ * distinct launch configurations per run). */
+lbm_status lbm_batch_bytes(int32_t precision, size_t* bytes);
+/* Group n (1..64) created and initialised contexts of one precision and one
+ * wall setting.  The contexts keep their buffers and stay usable on their
+ * own; dev_buf (>= lbm_batch_bytes, 256-byte aligned, caller-owned) holds the
+ * argument tables.  Work is ordered after / before the caller's hip_stream by
+ * events; the batch captures graphs on a stream of its own. */
+lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int32_t n, void* dev_buf, size_t bytes,
+                            void* hip_stream, lbm_batch** out);
+void lbm_batch_destroy(lbm_batch* b);
+const char* lbm_batch_last_error(const lbm_batch* b);
+/* Advance lattice g by steps[g] time steps: launch t advances every lattice
+ * with t < steps[g] in one multi-lattice kernel launch (the coarse levels run
+ * beside the fine ones).  use_graph != 0: repeated launch pairs are captured
+ * into a hipGraph once and replayed.  The result equals lbm_step() on each
+ * context (same kernels, same arithmetic).  Asynchronous. */
+lbm_status lbm_batch_run(lbm_batch* b, const int64_t* steps, int32_t use_graph);
+/* Device time of the last run (HIP events), number of step launches it
+ * covered and of graph launches used.  Waits for the run. */
+lbm_status lbm_batch_last_time(lbm_batch* b, double* ms, int64_t* kernel_launches,
+                               int64_t* graph_launches);
+
+/* Tile-height autotuner: times `steps` steps (after 2 warm-up steps) for each
+ * candidate tile_y with HIP events and keeps the fastest.  Advances the
+ * context's state by n * (steps + 2) steps, so run it on a throwaway context
+ * initialised like the real one. */
+lbm_status lbm_autotune_tile_y(lbm_ctx* ctx, const int32_t* candidates, int32_t n, int32_t steps,
+                               int32_t* best_tile_y, double* best_ms_per_step);
+
 /* ---- host parameter pipeline (Sec. 3); float64, no GPU ----------------- */
 /* T_c of Eq. peng-robinson's a = 0.45724 R^2 T_c^2/p_c, b = 0.0778 R T_c/p_c */
 double lbm_pr_critical_temperature(double a, double b, double R);
@@ -179,6 +217,20 @@ lbm_status lbm_fit_sigma(double a, double b, double R, double omega, double G, d
  * continuum profile of the normal balance. */
 lbm_status lbm_planar_gamma(double a, double b, double R, double omega, double G, double T,
                             double sigma, double* gamma0);
+
+/* One mesh of the refinement procedure (Sec. 3) relative to the base mesh
+ * (dx = dx_mesh / dx_base, e.g. 1/2 for a twice finer mesh):
+ *   a = a_base dx^2 (Eq. a-deltax), T = Tr T_c(a), Maxwell densities,
+ *   sigma from Eq. integral_coexistence_curve,
+ *   kappa from Eq. gamma-meshes-relation with gamma = (1 - kappa) gamma_0
+ *   (Eq. surface_tension, continuum planar profile), base kappa = kappa0,
+ *   g = gy0 dx^3 (Table 1), steps = steps0 / dx^2 (viscous regime). */
+typedef struct lbm_level {
+  double dx, a, Tc, T, rho_v, rho_l, p_sat, sigma, kappa, gamma, gy;
+  int64_t steps;
+} lbm_level;
+lbm_status lbm_refinement_level(double a_base, double dx, double Tr, double b, double R, double omega,
+                                double G, double kappa0, double gy0, int64_t steps0, lbm_level* out);
 
 #ifdef __cplusplus
 }

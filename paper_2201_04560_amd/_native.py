@@ -38,6 +38,11 @@ class LbmNorms(ctypes.Structure):
     ]
 
 
+class LbmLevel(ctypes.Structure):
+    _fields_ = [(k, c_double) for k in ("dx", "a", "Tc", "T", "rho_v", "rho_l", "p_sat", "sigma",
+                                        "kappa", "gamma", "gy")] + [("steps", c_int64)]
+
+
 # (name, restype, argtypes) of every exported symbol of include/lbm_pp.h
 P = ctypes.POINTER
 _DP = P(c_double)
@@ -62,6 +67,16 @@ SIGNATURES = [
     ("lbm_step_count", c_int64, [c_void_p]),
     ("lbm_last_step_time", c_int32, [c_void_p, _DP]),
     ("lbm_kernel_timing", c_int32, [c_void_p, c_int32]),
+    ("lbm_set_tile_y", c_int32, [c_void_p, c_int32]),
+    ("lbm_get_tile_y", c_int32, [c_void_p]),
+    ("lbm_batch_bytes", c_int32, [c_int32, P(c_size_t)]),
+    ("lbm_batch_create", c_int32, [P(c_void_p), c_int32, c_void_p, c_size_t, c_void_p, P(c_void_p)]),
+    ("lbm_batch_destroy", None, [c_void_p]),
+    ("lbm_batch_last_error", ctypes.c_char_p, [c_void_p]),
+    ("lbm_batch_run", c_int32, [c_void_p, P(c_int64), c_int32]),
+    ("lbm_batch_last_time", c_int32, [c_void_p, _DP, P(c_int64), P(c_int64)]),
+    ("lbm_autotune_tile_y", c_int32, [c_void_p, P(c_int32), c_int32, c_int32, P(c_int32), _DP]),
+    ("lbm_refinement_level", c_int32, [c_double] * 9 + [c_int64, P(LbmLevel)]),
     ("lbm_kernel_times", c_int32, [c_void_p, _DP, P(c_int64)]),
     ("lbm_pr_critical_temperature", c_double, [c_double, c_double, c_double]),
     ("lbm_pr_maxwell", c_int32, [c_double, c_double, c_double, c_double, c_double, _DP, _DP, _DP]),

@@ -1,6 +1,8 @@
 // Auxiliary kernels of the pseudopotential LBM library (gfx950): initial
 // state, the wall-closure mass correction needed by the mean density of
 // the buoyancy force, and the float64 diagnostic reductions.
+#include <cstring>
+
 #include "lbm_device.hpp"
 #include "lbm_kernels.hpp"
 
@@ -97,8 +99,8 @@ __device__ __forceinline__ double pulled_density(const S* f, long long pl, int p
 }
 
 template <class S, class C>
-__global__ __launch_bounds__(256) void lbm_wall_mass_kernel(WallArgs<S> A) {
-  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void wall_mass_body(const WallArgs<S>& A, const int bid) {
+  const int id = bid * blockDim.x + threadIdx.x;
   double dm = 0.0;
   uint32_t err = 0;
   if (id < 2 * A.nx) {
@@ -146,8 +148,24 @@ __global__ __launch_bounds__(256) void lbm_wall_mass_kernel(WallArgs<S> A) {
   if (threadIdx.x == 0) {
     double t = 0.0;
     for (int i = 0; i < int(blockDim.x / kLanes); ++i) t += red[i];
-    A.wall_out[blockIdx.x] = t;
+    A.wall_out[bid] = t;
   }
+}
+
+template <class S, class C>
+__global__ __launch_bounds__(256) void lbm_wall_mass_kernel(WallArgs<S> A) {
+  wall_mass_body<S, C>(A, blockIdx.x);
+}
+
+// batched version: workgroups [start[g], start[g+1]) serve lattice g
+template <class S, class C>
+__global__ __launch_bounds__(256) void lbm_wall_mass_multi_kernel(const WallArgs<S>* __restrict__ desc,
+                                                                  const int* __restrict__ start,
+                                                                  int ngrid) {
+  const int b = blockIdx.x;
+  int g = 0;
+  while (g + 1 < ngrid && b >= start[g + 1]) ++g;
+  wall_mass_body<S, C>(desc[g], b - start[g]);
 }
 
 // ---------------------------------------------------------------------
@@ -240,6 +258,31 @@ hipError_t launch_wall_mass(const LaunchWall& L, hipStream_t st) {
 
 hipError_t launch_norms(const NormArgs& a, int nblocks, hipStream_t st) {
   hipLaunchKernelGGL(lbm_norms_kernel, dim3(nblocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+size_t wall_desc_bytes(int fp32) { return fp32 ? sizeof(WallArgs<float>) : sizeof(WallArgs<double>); }
+
+void fill_wall_desc(const LaunchWall& L, void* out) {
+  if (L.fp32) {
+    WallArgs<float> a{static_cast<const float*>(L.fin), static_cast<const float*>(L.Tin), L.wall_out,
+                      L.tab, L.ph, L.nx, L.ny, L.pitch, L.plane};
+    std::memcpy(out, &a, sizeof a);
+  } else {
+    WallArgs<double> a{static_cast<const double*>(L.fin), static_cast<const double*>(L.Tin), L.wall_out,
+                       L.tab, L.ph, L.nx, L.ny, L.pitch, L.plane};
+    std::memcpy(out, &a, sizeof a);
+  }
+}
+
+hipError_t launch_wall_multi(int fp32, const void* desc, const int* start, int ngrid, int nblocks,
+                             hipStream_t st) {
+  if (fp32)
+    hipLaunchKernelGGL((lbm_wall_mass_multi_kernel<float, float>), dim3(nblocks), dim3(256), 0, st,
+                       static_cast<const WallArgs<float>*>(desc), start, ngrid);
+  else
+    hipLaunchKernelGGL((lbm_wall_mass_multi_kernel<double, double>), dim3(nblocks), dim3(256), 0, st,
+                       static_cast<const WallArgs<double>*>(desc), start, ngrid);
   return hipGetLastError();
 }
 

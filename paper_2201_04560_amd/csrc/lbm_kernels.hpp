@@ -109,4 +109,15 @@ hipError_t launch_norms(const NormArgs& a, int nblocks, hipStream_t st);
 int init_blocks(int nx, int ny);
 int wall_blocks(int nx);
 
+// batched launches over several lattices: per-lattice argument blocks are
+// filled on the host, copied to device memory and indexed by workgroup range
+size_t step_desc_bytes(int fp32);
+void fill_step_desc(const LaunchStep& L, void* out);
+hipError_t launch_step_multi(int fp32, int walls, int thermal, const void* desc, const int* start,
+                             int ngrid, int nblocks, hipStream_t st);
+size_t wall_desc_bytes(int fp32);
+void fill_wall_desc(const LaunchWall& L, void* out);
+hipError_t launch_wall_multi(int fp32, const void* desc, const int* start, int ngrid, int nblocks,
+                             hipStream_t st);
+
 }  // namespace lbm

@@ -182,4 +182,37 @@ lbm_status lbm_planar_gamma(double a, double b, double R, double omega, double G
   return LBM_OK;
 }
 
+lbm_status lbm_refinement_level(double a_base, double dx, double Tr, double b, double R, double omega,
+                                double G, double kappa0, double gy0, int64_t steps0, lbm_level* out) {
+  if (!out || !(dx > 0) || !(Tr > 0 && Tr < 1) || !(a_base > 0)) return LBM_E_INVAL;
+  lbm_level L{};
+  L.dx = dx;
+  // Eq. a-deltax: a = a_base (dx / dx0)^2, b fixed, T_c proportional to a
+  L.a = a_base * dx * dx;
+  L.Tc = lbm_pr_critical_temperature(L.a, b, R);
+  L.T = Tr * L.Tc;
+  lbm_status s = lbm_pr_maxwell(L.a, b, R, omega, L.T, &L.rho_v, &L.rho_l, &L.p_sat);
+  if (s != LBM_OK) return s;
+  // Eq. integral_coexistence_curve for sigma
+  s = lbm_fit_sigma(L.a, b, R, omega, G, L.T, &L.sigma);
+  if (s != LBM_OK) return s;
+  // Eq. gamma-meshes-relation: gamma(dx) = gamma(dx0) dx / dx0, with
+  // gamma = (1 - kappa) gamma(kappa = 0) from Eq. surface_tension
+  double base_sigma, g_base, g0;
+  const double Tb = Tr * lbm_pr_critical_temperature(a_base, b, R);
+  s = lbm_fit_sigma(a_base, b, R, omega, G, Tb, &base_sigma);
+  if (s != LBM_OK) return s;
+  s = lbm_planar_gamma(a_base, b, R, omega, G, Tb, base_sigma, &g_base);
+  if (s != LBM_OK) return s;
+  s = lbm_planar_gamma(L.a, b, R, omega, G, L.T, L.sigma, &g0);
+  if (s != LBM_OK) return s;
+  L.gamma = (1.0 - kappa0) * g_base * dx;
+  L.kappa = dx == 1.0 ? kappa0 : 1.0 - L.gamma / g0;
+  // Table 1: g ~ dx^3; viscous regime: steps ~ dx^-2
+  L.gy = gy0 * dx * dx * dx;
+  L.steps = int64_t(std::llround(double(steps0) / (dx * dx)));
+  *out = L;
+  return LBM_OK;
+}
+
 }  // extern "C"

@@ -11,7 +11,7 @@
 #include <vector>
 
 #include "../../include/lbm_pp.h"
-#include "lbm_kernels.hpp"
+#include "lbm_internal.hpp"
 
 using namespace lbm;
 
@@ -22,17 +22,6 @@ constexpr uint64_t kStateMagic = 0x314D424C50504E42ull;  // "BNPPLBM1"
 constexpr int kNormBlocks = 512;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
-struct Layout {
-  int pitch = 0;
-  long long plane = 0;  // elements between population planes
-  int elem = 8;         // bytes per stored value
-  int ty = 0, ntx = 0, nty = 0, nblocks = 0;
-  int part_cap = 0, wall_cap = 0;
-  size_t off_f[2] = {0, 0}, off_T[2] = {0, 0};
-  size_t off_tab = 0, off_tk = 0, off_part[2] = {0, 0}, off_wall = 0, off_red = 0, off_err = 0;
-  size_t total = 0;
-};
 
 int default_tile_y(int nx, int ny, int walls) {
   // aim at ~8 one-wave workgroups per CU; small lattices get short strips
@@ -47,7 +36,9 @@ int default_tile_y(int nx, int ny, int walls) {
   return std::max(2, std::min(ty, std::max(ny, 2)));
 }
 
-void make_layout(const lbm_params& p, Layout& L) {
+}  // namespace
+
+void lbm::make_layout(const lbm_params& p, Layout& L) {
   L.elem = p.precision == LBM_FP32_SHIFTED ? 4 : 8;
   L.pitch = int(align_up(size_t(p.nx), 64));
   // plane stride: padded off powers of two so that the 9 loads of a node
@@ -58,7 +49,9 @@ void make_layout(const lbm_params& p, Layout& L) {
   L.ntx = (p.nx + tile_x(p.walls) - 1) / tile_x(p.walls);
   L.nty = (p.ny + L.ty - 1) / L.ty;
   L.nblocks = L.ntx * L.nty;
-  L.part_cap = std::max(L.nblocks, init_blocks(p.nx, p.ny));
+  // partial sums for the shortest allowed strips (tile_y = 2): the tile
+  // height can be changed after creation
+  L.part_cap = std::max(L.ntx * ((p.ny + 1) / 2) + 8, init_blocks(p.nx, p.ny));
   L.wall_cap = wall_blocks(p.nx);
   size_t o = 0;
   const size_t fbytes = align_up(size_t(9 * L.plane) * L.elem, kAlign);
@@ -73,6 +66,8 @@ void make_layout(const lbm_params& p, Layout& L) {
   L.off_err = o; o += kAlign;
   L.total = o;
 }
+
+namespace {
 
 Phys make_phys(const lbm_params& p) {
   Phys h{};
@@ -113,58 +108,7 @@ std::string g_create_error;
 
 }  // namespace
 
-struct lbm_ctx {
-  lbm_params p{};
-  Layout L;
-  Phys ph{};
-  hipStream_t stream = nullptr;
-  char* base = nullptr;
-  size_t bytes = 0;
-  int cur = 0, Tcur = 0, pcur = 0, npart = 0;
-  int64_t step = 0;
-  bool initialized = false;
-  std::vector<double> rw_b, rw_t, tv_b, tv_t;
-  std::vector<int32_t> tk_b, tk_t;
-  std::string err;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  bool timed = false;
-  // optional per-launch timing of the step kernel (event pairs on the stream)
-  bool ktime = false;
-  std::vector<hipEvent_t> kev;
-  size_t kused = 0;
-
-  void* f(int i) const { return base + L.off_f[i]; }
-  void* T(int i) const { return base + L.off_T[i]; }
-  double* part(int i) const { return reinterpret_cast<double*>(base + L.off_part[i]); }
-  double* wall() const { return reinterpret_cast<double*>(base + L.off_wall); }
-  double* red() const { return reinterpret_cast<double*>(base + L.off_red); }
-  uint32_t* errp() const { return reinterpret_cast<uint32_t*>(base + L.off_err); }
-  double* tabd() const { return reinterpret_cast<double*>(base + L.off_tab); }
-  int32_t* tabi() const { return reinterpret_cast<int32_t*>(base + L.off_tk); }
-  Tables tables() const {
-    Tables t;
-    const int nx = p.nx;
-    t.rho_w_b = tabd();
-    t.rho_w_t = tabd() + nx;
-    t.tv_b = tabd() + 2 * nx;
-    t.tv_t = tabd() + 3 * nx;
-    t.tk_b = tabi();
-    t.tk_t = tabi() + nx;
-    return t;
-  }
-  size_t staging_bytes() const { return size_t(9 * L.plane) * L.elem; }
-};
-
-#define HIP_TRY(ctx, expr)                                                     \
-  do {                                                                         \
-    hipError_t e_ = (expr);                                                    \
-    if (e_ != hipSuccess) {                                                    \
-      (ctx)->err = std::string(#expr) + ": " + hipGetErrorString(e_);          \
-      return LBM_E_HIP;                                                        \
-    }                                                                          \
-  } while (0)
-
-static lbm_status fail(lbm_ctx* c, lbm_status s, const std::string& msg) {
+lbm_status lbm::fail(lbm_ctx* c, lbm_status s, const std::string& msg) {
   if (c) c->err = msg; else g_create_error = msg;
   return s;
 }
@@ -405,7 +349,9 @@ lbm_status lbm_init_fields(lbm_ctx* c, const double* rho, const double* ux, cons
   return LBM_OK;
 }
 
-static LaunchStep step_args(lbm_ctx* c) {
+}  // extern "C"
+
+LaunchStep lbm::step_args(lbm_ctx* c) {
   LaunchStep L{};
   L.fp32 = c->p.precision == LBM_FP32_SHIFTED;
   L.fin = c->f(c->cur);
@@ -434,6 +380,37 @@ static LaunchStep step_args(lbm_ctx* c) {
   return L;
 }
 
+
+LaunchWall lbm::wall_args(lbm_ctx* c, const LaunchStep& L) {
+  LaunchWall W{};
+  W.fp32 = L.fp32;
+  W.fin = L.fin;
+  W.Tin = L.Tin;
+  W.wall_out = c->wall();
+  W.tab = L.tab;
+  W.ph = c->ph;
+  W.nx = c->p.nx;
+  W.ny = c->p.ny;
+  W.pitch = c->L.pitch;
+  W.plane = c->L.plane;
+  return W;
+}
+
+extern "C" {
+
+lbm_status lbm_set_tile_y(lbm_ctx* c, int32_t tile_y) {
+  if (!c) return LBM_E_INVAL;
+  if (tile_y < 2) return fail(c, LBM_E_INVAL, "tile_y must be >= 2");
+  const int nty = (c->p.ny + tile_y - 1) / tile_y;
+  if (c->L.ntx * nty + 8 > c->L.part_cap) return fail(c, LBM_E_INVAL, "tile_y too small for the buffer");
+  c->L.ty = tile_y;
+  c->L.nty = nty;
+  c->L.nblocks = c->L.ntx * nty;
+  return LBM_OK;
+}
+
+int32_t lbm_get_tile_y(const lbm_ctx* c) { return c ? c->L.ty : -1; }
+
 lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
   if (!c) return LBM_E_INVAL;
   if (!c->initialized) return fail(c, LBM_E_STATE, "lbm_step before lbm_init_fields");
@@ -445,18 +422,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
     L.update_T = c->p.thermal && c->step >= c->p.n_iso;
     L.want_mass = grav;
     if (grav && c->p.walls) {
-      LaunchWall W{};
-      W.fp32 = L.fp32;
-      W.fin = L.fin;
-      W.Tin = L.Tin;
-      W.wall_out = c->wall();
-      W.tab = L.tab;
-      W.ph = c->ph;
-      W.nx = c->p.nx;
-      W.ny = c->p.ny;
-      W.pitch = c->L.pitch;
-      W.plane = c->L.plane;
-      HIP_TRY(c, launch_wall_mass(W, c->stream));
+      HIP_TRY(c, launch_wall_mass(wall_args(c, L), c->stream));
       L.nwall_in = wall_blocks(c->p.nx);
     }
     if (c->ktime) {
@@ -535,18 +501,7 @@ static lbm_status run_macro(lbm_ctx* c, double* o_rho, double* o_ux, double* o_u
   L.f_first = f_first;
   L.f_count = f_count;
   if (c->ph.gy != 0.0 && c->p.walls) {
-    LaunchWall W{};
-    W.fp32 = L.fp32;
-    W.fin = L.fin;
-    W.Tin = L.Tin;
-    W.wall_out = c->wall();
-    W.tab = L.tab;
-    W.ph = c->ph;
-    W.nx = c->p.nx;
-    W.ny = c->p.ny;
-    W.pitch = c->L.pitch;
-    W.plane = c->L.plane;
-    HIP_TRY(c, launch_wall_mass(W, c->stream));
+    HIP_TRY(c, launch_wall_mass(wall_args(c, L), c->stream));
     L.nwall_in = wall_blocks(c->p.nx);
   }
   HIP_TRY(c, launch_macro(L, c->stream));

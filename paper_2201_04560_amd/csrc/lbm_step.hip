@@ -25,6 +25,7 @@
 // Storage S is double (plain step) or float (populations stored as
 // g_i = f_i - w_i rho_ref).  C is the type of the collision and energy
 // arithmetic.  EOS, psi, forces and Q are float64 in both.
+#include <cstring>
 #include <type_traits>
 
 #include "lbm_device.hpp"
@@ -130,12 +131,13 @@ __device__ constexpr int sl(int ph, int delta) { return (ph - delta) & 3; }
 template <int N>
 using Ph = std::integral_constant<int, N>;
 
+// one strip of one lattice; bid is the workgroup's index within its lattice
 template <class S, class C, bool WALLS, bool THERMAL, int MODE>
-__global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(WavesPerEU<S>::value, 8)))
-void lbm_march_kernel(StepArgs<S, C> A, MacroOut O) {
+__device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroOut& O, const int bid) {
   const int lane = threadIdx.x;
   const int nb = A.ntx * A.nty;
-  const int tile = tile_of_block(blockIdx.x, nb, A.xcd_remap);
+  if (bid >= nb) return;  // padding workgroup of a batched launch
+  const int tile = tile_of_block(bid, nb, A.xcd_remap);
   const int tx = tile % A.ntx, tyi = tile / A.ntx;
   const int nx = A.nx, ny = A.ny;
   constexpr int halo = WALLS ? 4 : 3;
@@ -613,7 +615,7 @@ void lbm_march_kernel(StepArgs<S, C> A, MacroOut O) {
 
   if (MODE == MODE_STEP && A.want_mass) {
     const double tot = wave_sum(mass_acc);
-    if (lane == 0) A.part_out[blockIdx.x] = tot;
+    if (lane == 0) A.part_out[bid] = tot;
   }
   const unsigned long long any = __ballot(err != 0);
   if (any) {
@@ -622,6 +624,28 @@ void lbm_march_kernel(StepArgs<S, C> A, MacroOut O) {
     for (int off = 32; off > 0; off >>= 1) e |= __shfl_xor(e, off, kLanes);
     if (lane == 0) atomicOr(A.err, e);
   }
+}
+
+template <class S, class C, bool WALLS, bool THERMAL, int MODE>
+__global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(WavesPerEU<S>::value, 8)))
+void lbm_march_kernel(StepArgs<S, C> A, MacroOut O) {
+  march_body<S, C, WALLS, THERMAL, MODE>(A, O, blockIdx.x);
+}
+
+// Batched launch over several lattices of one kind (same storage, walls and
+// energy flags): workgroups [start[g], start[g+1]) serve lattice g, whose
+// arguments are read from the descriptor table in device memory.  Each
+// lattice's workgroup count is padded to a multiple of 8 so that the XCD of
+// a workgroup is the same as in a single-lattice launch.
+template <class S, class C, bool WALLS, bool THERMAL>
+__global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(WavesPerEU<S>::value, 8)))
+void lbm_march_multi_kernel(const StepArgs<S, C>* __restrict__ desc, const int* __restrict__ start,
+                            int ngrid) {
+  const int b = blockIdx.x;
+  int g = 0;
+  while (g + 1 < ngrid && b >= start[g + 1]) ++g;
+  const MacroOut O{};
+  march_body<S, C, WALLS, THERMAL, MODE_STEP>(desc[g], O, b - start[g]);
 }
 
 // ------------------------------------------------------------- launchers
@@ -653,7 +677,7 @@ static void launch_one(const StepArgs<S, C>& a, const MacroOut& o, int nblocks, 
 }
 
 template <class S, class C>
-static hipError_t launch_step_t(const LaunchStep& L, hipStream_t st, int mode) {
+static StepArgs<S, C> make_args(const LaunchStep& L) {
   StepArgs<S, C> a{};
   a.fin = static_cast<const S*>(L.fin);
   a.fout = static_cast<S*>(L.fout);
@@ -680,6 +704,12 @@ static hipError_t launch_step_t(const LaunchStep& L, hipStream_t st, int mode) {
   a.xcd_remap = L.xcd_remap;
   a.ph = L.ph;
   a.pc = phys_c<C>(L.ph);
+  return a;
+}
+
+template <class S, class C>
+static hipError_t launch_step_t(const LaunchStep& L, hipStream_t st, int mode) {
+  const StepArgs<S, C> a = make_args<S, C>(L);
   MacroOut o{L.o_rho, L.o_ux, L.o_uy, L.o_T, L.o_f, L.f_first, L.f_count};
   const int nb = L.ntx * L.nty;
   if (mode == MODE_MACRO) {
@@ -703,6 +733,48 @@ hipError_t launch_step(const LaunchStep& L, hipStream_t st) {
 hipError_t launch_macro(const LaunchStep& L, hipStream_t st) {
   return L.fp32 ? launch_step_t<float, float>(L, st, MODE_MACRO)
                 : launch_step_t<double, double>(L, st, MODE_MACRO);
+}
+
+size_t step_desc_bytes(int fp32) {
+  return fp32 ? sizeof(StepArgs<float, float>) : sizeof(StepArgs<double, double>);
+}
+
+void fill_step_desc(const LaunchStep& L, void* out) {
+  if (L.fp32) {
+    const StepArgs<float, float> a = make_args<float, float>(L);
+    std::memcpy(out, &a, sizeof a);
+  } else {
+    const StepArgs<double, double> a = make_args<double, double>(L);
+    std::memcpy(out, &a, sizeof a);
+  }
+}
+
+template <class S, class C, bool WALLS, bool THERMAL>
+static void launch_multi_t(const void* desc, const int* start, int ngrid, int nblocks, hipStream_t st) {
+  hipLaunchKernelGGL((lbm_march_multi_kernel<S, C, WALLS, THERMAL>), dim3(nblocks), dim3(kLanes), 0, st,
+                     static_cast<const StepArgs<S, C>*>(desc), start, ngrid);
+}
+
+hipError_t launch_step_multi(int fp32, int walls, int thermal, const void* desc, const int* start,
+                             int ngrid, int nblocks, hipStream_t st) {
+  if (fp32) {
+    if (walls) {
+      if (thermal) launch_multi_t<float, float, true, true>(desc, start, ngrid, nblocks, st);
+      else launch_multi_t<float, float, true, false>(desc, start, ngrid, nblocks, st);
+    } else {
+      if (thermal) launch_multi_t<float, float, false, true>(desc, start, ngrid, nblocks, st);
+      else launch_multi_t<float, float, false, false>(desc, start, ngrid, nblocks, st);
+    }
+  } else {
+    if (walls) {
+      if (thermal) launch_multi_t<double, double, true, true>(desc, start, ngrid, nblocks, st);
+      else launch_multi_t<double, double, true, false>(desc, start, ngrid, nblocks, st);
+    } else {
+      if (thermal) launch_multi_t<double, double, false, true>(desc, start, ngrid, nblocks, st);
+      else launch_multi_t<double, double, false, false>(desc, start, ngrid, nblocks, st);
+    }
+  }
+  return hipGetLastError();
 }
 
 }  // namespace lbm

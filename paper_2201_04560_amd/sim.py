@@ -5,7 +5,7 @@ import ctypes
 import numpy as np
 
 from . import _native as nat
-from ._native import LbmNorms, LbmParams, check, lib
+from ._native import LbmError, LbmNorms, LbmParams, check, lib
 
 
 def make_params(nx, ny, **kw):
@@ -143,6 +143,29 @@ class Lattice:
               "lbm_kernel_times")
         return s.value, n.value
 
+    @property
+    def tile_y(self):
+        """Rows per workgroup strip of the step kernel."""
+        return lib().lbm_get_tile_y(self._ctx)
+
+    @tile_y.setter
+    def tile_y(self, ty):
+        check(lib().lbm_set_tile_y(self._ctx, int(ty)), self._ctx, "lbm_set_tile_y")
+
+    def autotune_tile_y(self, candidates=(2, 3, 4, 6, 8, 12, 16, 24, 32), steps=20):
+        """Time each candidate strip height on this lattice and keep the
+        fastest.  The state is saved first and restored afterwards, so the
+        simulation is not advanced.  Returns (tile_y, ms per step)."""
+        state = self.save_state()
+        cand = [int(c) for c in candidates if int(c) >= 2]
+        arr = (ctypes.c_int32 * len(cand))(*cand)
+        best, ms = ctypes.c_int32(), ctypes.c_double()
+        check(lib().lbm_autotune_tile_y(self._ctx, arr, len(cand), int(steps), ctypes.byref(best),
+                                        ctypes.byref(ms)), self._ctx, "lbm_autotune_tile_y")
+        self.load_state(state)
+        self.tile_y = best.value
+        return best.value, ms.value
+
     def save_state(self):
         n = ctypes.c_size_t()
         check(lib().lbm_state_bytes(self._ctx, ctypes.byref(n)), self._ctx, "lbm_state_bytes")
@@ -155,6 +178,62 @@ class Lattice:
         buf = np.ascontiguousarray(buf, dtype=np.uint8)
         check(lib().lbm_load_state(self._ctx, buf.ctypes.data_as(ctypes.c_void_p), buf.size),
               self._ctx, "lbm_load_state")
+
+
+class Batch:
+    """Several lattices of one precision and wall setting advanced together:
+    each launch steps every lattice that still has steps to do, so the
+    coarse meshes of a refinement ladder ride along with the fine ones."""
+
+    def __init__(self, lattices, stream=None):
+        import torch
+
+        if not lattices:
+            raise ValueError("empty batch")
+        self.lattices = list(lattices)
+        prec = self.lattices[0].p.precision
+        n = ctypes.c_size_t()
+        check(lib().lbm_batch_bytes(prec, ctypes.byref(n)), None, "lbm_batch_bytes")
+        dev = self.lattices[0]._buf.device
+        self._buf = torch.empty(n.value + 256, dtype=torch.uint8, device=dev)
+        aligned = (self._buf.data_ptr() + 255) // 256 * 256
+        self._stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        ctxs = (ctypes.c_void_p * len(self.lattices))(*[l._ctx.value for l in self.lattices])
+        self._b = ctypes.c_void_p()
+        st = lib().lbm_batch_create(ctxs, len(self.lattices), ctypes.c_void_p(aligned), n.value,
+                                    ctypes.c_void_p(self._stream.cuda_stream), ctypes.byref(self._b))
+        if st != 0:
+            raise LbmError(st, f"lbm_batch_create: {(lib().lbm_last_error(self.lattices[0]._ctx) or b'').decode()}")
+
+    def _check(self, st, what):
+        if st != 0:
+            detail = lib().lbm_batch_last_error(self._b) or b""
+            raise LbmError(st, f"{what}: {detail.decode()}")
+
+    def run(self, steps, use_graph=True):
+        """Advance lattice g by steps[g] steps (asynchronous)."""
+        if len(steps) != len(self.lattices):
+            raise ValueError("one step count per lattice")
+        arr = (ctypes.c_int64 * len(steps))(*[int(s) for s in steps])
+        self._check(lib().lbm_batch_run(self._b, arr, 1 if use_graph else 0), "lbm_batch_run")
+
+    def last_time(self):
+        """(device ms, step launches, graph launches) of the last run."""
+        ms, nl, ng = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
+        self._check(lib().lbm_batch_last_time(self._b, ctypes.byref(ms), ctypes.byref(nl),
+                                              ctypes.byref(ng)), "lbm_batch_last_time")
+        return ms.value, nl.value, ng.value
+
+    def close(self):
+        if getattr(self, "_b", None) is not None and self._b.value:
+            lib().lbm_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ------------------------------------------------------------ host helpers
@@ -180,3 +259,13 @@ def planar_gamma(a, T, sigma, b=2.0 / 21.0, R=1.0, omega=0.344, G=-1.0):
     check(lib().lbm_planar_gamma(a, b, R, omega, G, T, sigma, ctypes.byref(g)), None,
           "lbm_planar_gamma")
     return g.value
+
+
+def refinement_level(a_base, dx, Tr=0.86, kappa0=0.0, gy0=0.0, steps0=0, b=2.0 / 21.0, R=1.0,
+                     omega=0.344, G=-1.0):
+    """Parameters of a mesh dx times the base spacing (Sec. 3): a, T_c, T,
+    Maxwell densities, sigma, kappa, target gamma, gravity and step count."""
+    L = nat.LbmLevel()
+    check(lib().lbm_refinement_level(a_base, dx, Tr, b, R, omega, G, kappa0, gy0, int(steps0),
+                                     ctypes.byref(L)), None, "lbm_refinement_level")
+    return {k: getattr(L, k) for k, _ in nat.LbmLevel._fields_}

@@ -107,9 +107,48 @@ def test_host_parameter_pipeline_matches_oracle(lib, a):
     assert abs(pp.planar_gamma(a, T, s) / g - 1) < 1e-7
 
 
+def test_refinement_levels_match_oracle(lib):
+    """Per-mesh a, Maxwell densities, sigma and kappa of the refinement
+    ladder (Sec. 3) from the library against the oracle's independent
+    implementation; the printed droplet meshes L = 128..432."""
+    import paper_2201_04560_amd as pp
+
+    a0 = 6.12e-3
+    ref = th.refinement_parameters(a0, 128, [128, 192, 288, 432])
+    for o in ref:
+        lv = pp.refinement_level(a0, 128 / o["L"], gy0=-2.5e-5, steps0=400000)
+        assert abs(lv["a"] / o["a"] - 1) < 1e-14
+        assert abs(lv["rho_v"] - o["rho_v"]) < 1e-11 and abs(lv["rho_l"] - o["rho_l"]) < 1e-10
+        assert abs(lv["sigma"] - o["sigma"]) < 1e-9
+        assert abs(lv["kappa"] - o["kappa"]) < 1e-6, (o["L"], lv["kappa"], o["kappa"])
+        assert abs(lv["gy"] / (-2.5e-5 * (128 / o["L"]) ** 3) - 1) < 1e-14
+        assert lv["steps"] == round(400000 * (o["L"] / 128) ** 2)
+
+
 def test_host_pipeline_rejects_supercritical(lib):
     import paper_2201_04560_amd as pp
     from paper_2201_04560_amd import LbmError
 
     with pytest.raises(LbmError):
         pp.pr_maxwell(2.0 / 49.0, 1.01 * pp.pr_critical_temperature(2.0 / 49.0))
+
+
+def test_pool_ladder_levels(lib):
+    """Mesh k of the ladder: 2^k times the base size, a ~ dx^2, g ~ dx^3,
+    steps ~ dx^-2, heater strip an eighth of the width at 0.95 T_c(a_k)."""
+    from paper_2201_04560_amd.ladder import pool_level
+
+    base = pool_level(0, steps0=50)
+    for k in range(4):
+        L = pool_level(k, steps0=50)
+        p, lv = L["params"], L["level"]
+        assert (L["nx"], L["ny"]) == (128 * 2 ** k, 256 * 2 ** k) == (p.nx, p.ny)
+        assert abs(p.a / base["params"].a - 4.0 ** -k) < 1e-15
+        assert abs(p.gy / base["params"].gy - 8.0 ** -k) < 1e-14
+        assert L["steps"] == 50 * 4 ** k
+        h0, h1 = L["heater"]
+        assert h1 - h0 == L["nx"] // 8
+        tb = L["boundary"]["t_bottom_val"]
+        assert abs(tb[h0] / lv["Tc"] - 0.95) < 1e-14 and abs(tb[0] / lv["Tc"] - 0.86) < 1e-14
+        assert p.precision == 1 and p.walls == 1 and p.thermal == 1
+        assert abs(p.rho_v - base["params"].rho_v) < 1e-10

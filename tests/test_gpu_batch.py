@@ -1,0 +1,131 @@
+"""Batched lattices (the refinement ladder of Sec. 3 in one launch per time
+step) and the tile autotuner, through the C-ABI.
+
+A batch runs the same kernels with the same arithmetic as lbm_step on each
+context, so the result must be bit-identical to stepping each lattice on
+its own, with and without graph replay."""
+import numpy as np
+import pytest
+
+import cases
+
+pytestmark = pytest.mark.gpu
+
+
+def _pool_case(nx, ny, seed, thermal=True, gy=-3e-5, n_iso=0):
+    eos, Tsat, rv, rl = cases.coexistence()
+    kb = np.full(nx, 2)
+    vb = np.full(nx, Tsat)
+    rwb = np.full(nx, 6.5)
+    h0, h1 = nx // 3, 2 * nx // 3
+    kb[h0:h1] = 1
+    vb[h0:h1] = 0.95 * eos.Tc
+    rwb[h0:h1] = 3.44
+    c = dict(nx=nx, ny=ny, a=2.0 / 49.0, sigma=0.1103, kappa=0.05, rho_l=rl, rho_v=rv, walls=True,
+             thermal=thermal, n_iso=n_iso, gy=gy, cv=5.0, lambda_l=1.95, lambda_v=0.114,
+             rho_w_bottom=rwb, rho_w_top=0.38, t_bottom_kind=kb, t_bottom_val=vb,
+             t_top_kind=np.full(nx, 1), t_top_val=np.full(nx, Tsat), **cases.wl.POOL_RATES)
+    rho, T = cases.wl.pool(nx, ny, 0.6 * ny, 2.3, rl, rv, Tsat, seed_radius=5.0, seed=seed)
+    return c, rho, T
+
+
+def _drop_case(n, seed):
+    eos, Tsat, rv, rl = cases.coexistence()
+    Tout = 0.95 * eos.Tc
+    c = dict(nx=n, ny=n, a=2.0 / 49.0, sigma=0.1, kappa=0.1, rho_l=rl, rho_v=rv, thermal=True,
+             cv=6.0, lambda_l=2 / 3, lambda_v=2 / 3, t_side_dirichlet=True, t_side_val=Tout,
+             t_bottom_kind=np.full(n, 1), t_bottom_val=np.full(n, Tout),
+             t_top_kind=np.full(n, 1), t_top_val=np.full(n, Tout), **cases.wl.DROPLET_RATES)
+    rho, T = cases.wl.droplet(n, n, n / 5, 4.6 / 5.0, rl, rv, Tsat, Tout, seed=seed)
+    return c, rho, T
+
+
+def _make(case, precision=0, tile_y=0):
+    from paper_2201_04560_amd import Lattice
+
+    c, rho, T = case
+    lat = Lattice(cases.lib_params(c, precision=precision, tile_y=tile_y))
+    cases.lib_boundary(lat, c)
+    lat.init_fields(rho, None, None, T)
+    return lat
+
+
+def _run_pair(case_list, steps, precision, use_graph, tiles=None, runs=1):
+    from paper_2201_04560_amd import Batch
+
+    tiles = tiles or [0] * len(case_list)
+    solo = [_make(cs, precision, ty) for cs, ty in zip(case_list, tiles)]
+    grouped = [_make(cs, precision, ty) for cs, ty in zip(case_list, tiles)]
+    b = Batch(grouped)
+    for _ in range(runs):
+        for lat, n in zip(solo, steps):
+            lat.step(n)
+        b.run(steps, use_graph=use_graph)
+    ms, launches, graphs = b.last_time()
+    print(f"batch ms={ms:.3f} launches={launches} graph_launches={graphs}", flush=True)
+    # one launch per step, two where lattices with and without the energy
+    # update share a step
+    assert max(steps) <= launches <= 2 * max(steps)
+    if use_graph and max(steps) >= 8:
+        assert graphs > 0
+    for g, (a, bl) in enumerate(zip(solo, grouped)):
+        assert bl.step_count == a.step_count == runs * steps[g]
+        fa, fb = a.populations(), bl.populations()
+        Ta, Tb = a.fields()[3], bl.fields()[3]
+        assert np.array_equal(fa, fb), (g, np.abs(fa - fb).max())
+        assert np.array_equal(Ta, Tb), (g, np.abs(Ta - Tb).max())
+    b.close()
+    return ms, launches, graphs
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_walls_gravity_matches_solo(precision, use_graph):
+    """Three wall-bounded lattices of different sizes, one isothermal for its
+    first steps (n_iso), one isothermal throughout; gravity on, so the
+    wall-mass pre-kernel and rho_bar partials are batched too."""
+    print(f"case batch walls precision={precision} graph={use_graph}", flush=True)
+    cs = [_pool_case(80, 48, 1), _pool_case(64, 40, 2, n_iso=9), _pool_case(96, 32, 3, thermal=False)]
+    _run_pair(cs, [37, 25, 11], precision, use_graph, tiles=[8, 5, 0], runs=2)
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_periodic_matches_solo_fp32(use_graph):
+    print(f"case batch periodic fp32 graph={use_graph}", flush=True)
+    cs = [_drop_case(64, 1), _drop_case(96, 2), _drop_case(40, 3), _drop_case(130, 4)]
+    _run_pair(cs, [20, 45, 9, 30], 1, use_graph)
+
+
+def test_batch_single_lattice_long_graph_replay():
+    """One lattice, many steps: the replay path (repeated launch pairs)."""
+    print("case batch single long", flush=True)
+    _run_pair([_pool_case(72, 40, 5)], [301], 0, True)
+
+
+def test_batch_rejects_mixed_settings():
+    print("case batch reject", flush=True)
+    from paper_2201_04560_amd import Batch, LbmError
+
+    a = _make(_pool_case(40, 24, 1))
+    b = _make(_drop_case(40, 2))
+    with pytest.raises(LbmError):
+        Batch([a, b])
+    c = _make(_drop_case(40, 3), precision=1)
+    with pytest.raises(LbmError):
+        Batch([b, c])
+
+
+def test_autotune_keeps_state():
+    print("case autotune", flush=True)
+    lat = _make(_pool_case(96, 64, 7, gy=0.0))
+    lat.step(3)
+    before = lat.populations()
+    ty, ms = lat.autotune_tile_y(candidates=(2, 4, 8, 16), steps=5)
+    print(f"autotune best tile_y={ty} ms={ms:.4f}", flush=True)
+    assert ty in (2, 4, 8, 16) and ms > 0
+    assert lat.tile_y == ty and lat.step_count == 3
+    assert np.array_equal(before, lat.populations())
+    ref = _make(_pool_case(96, 64, 7, gy=0.0), tile_y=ty)
+    ref.step(8)
+    lat.step(5)
+    assert np.array_equal(ref.populations(), lat.populations())
