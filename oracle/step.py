@@ -131,6 +131,8 @@ class Params:
         def col(v, fill, dt=np.float64):
             if v is None:
                 return np.full(nx, fill, dtype=dt)
+            if dt is np.float64 and np.iscomplexobj(v):
+                dt = np.complex128  # complex-step differentiation (oracle/adjoint.py)
             v = np.asarray(v, dtype=dt)
             return np.full(nx, v, dtype=dt) if v.ndim == 0 else v.copy()
         self.rho_w_bottom = col(self.rho_w_bottom, 1.0)
@@ -163,7 +165,7 @@ class Sim:
         p = self.p
         ny, nx = p.ny, p.nx
         kind = np.zeros((ny, nx), dtype=np.int64)
-        val = np.zeros((ny, nx), dtype=np.float64)
+        val = np.zeros((ny, nx), dtype=np.result_type(p.t_bottom_val, p.t_top_val, np.float64))
         kind[0, :] = p.t_bottom_kind
         val[0, :] = p.t_bottom_val
         kind[ny - 1, :] = p.t_top_kind
