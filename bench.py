@@ -267,6 +267,77 @@ def ladder_bench(steps0, levels=(0, 1, 2, 3), seeds=(0, 1, 2, 3), tile_cache=Non
                         "per mesh over its 4 seeds, after the full schedule"}
 
 
+def adjoint_case(n=256, seed=0):
+    """Droplet vaporisation on n x n (radius 60 n / 512, as the 512^2
+    workload) whose bottom ring row is the heater profile (0.95 T_c)."""
+    import paper_2201_04560_amd as pp
+    import workloads as wl
+
+    a = 2.0 / 49.0
+    Tc = pp.pr_critical_temperature(a)
+    Tsat, Tout = 0.86 * Tc, 0.95 * Tc
+    rv, rl, _ = pp.pr_maxwell(a, Tsat)
+    rho, T = wl.droplet(n, n, 60.0 * n / 512, 4.6 / 5.0, rl, rv, Tsat, Tout, seed=seed)
+    kw = dict(a=a, sigma=0.1, kappa=0.1, rho_l=rl, rho_v=rv, thermal=1, cv=6.0, lambda_l=2.0 / 3.0,
+              lambda_v=2.0 / 3.0, t_side_dirichlet=1, t_side_val=Tout, rho_ref=rv)
+    kw.update(wl.DROPLET_RATES)
+    bnd = dict(t_bottom_kind=np.full(n, 1, np.int32), t_bottom_val=np.full(n, Tout),
+               t_top_kind=np.full(n, 1, np.int32), t_top_val=np.full(n, Tout))
+    return n, kw, bnd, rho, T
+
+
+def adjoint_bench(nsteps=500, ckpt=50, n=256, fd_entries=8, h=1e-4):
+    """Heater-profile gradient of the evaporated mass: cost of the adjoint
+    against the plain forward, check against central differences."""
+    import torch
+
+    from paper_2201_04560_amd import HeaterProblem, make_params
+
+    n, kw, bnd, rho, T = adjoint_case(n)
+    out = {"workload": f"droplet vaporisation {n}x{n}, {nsteps} steps, checkpoint every {ckpt}, "
+                       f"gradient of the evaporated liquid mass w.r.t. the {n}-entry bottom heater "
+                       "profile"}
+    grads = {}
+    for name, prec in (("fp32", 1), ("fp64", 0)):
+        pr = HeaterProblem(make_params(n, n, precision=prec, **kw), bnd, rho, T, nsteps, ckpt)
+        tb = bnd["t_bottom_val"]
+        pr.run(tb)  # warm-up (module load, first-touch)
+        pr.adjoint.backward()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pr.lattice.set_boundary(**bnd)
+        pr.lattice.init_fields(rho, None, None, T)
+        pr.lattice.step(nsteps)
+        pr.lattice.sync()
+        t_plain = time.perf_counter() - t0
+        J = pr.run(tb)
+        g = pr.adjoint.backward()
+        f_ms, b_ms = pr.adjoint.timing()
+        grads[name] = g
+        out[name] = {"J": J, "plain_forward_ms": round(t_plain * 1e3, 3),
+                     "checkpointed_forward_ms": round(f_ms, 3), "backward_ms": round(b_ms, 3),
+                     "backward_over_forward": round(b_ms / (t_plain * 1e3), 2),
+                     "gradient_over_forward": round((f_ms + b_ms) / (t_plain * 1e3), 2),
+                     "speedup_vs_central_fd": round(2 * n * t_plain * 1e3 / (f_ms + b_ms), 1)}
+        if name == "fp64":
+            ent = np.linspace(16, n - 17, fd_entries).astype(int)
+            errs = []
+            for x in ent:
+                tp, tm = tb.copy(), tb.copy()
+                tp[x] += h
+                tm[x] -= h
+                fd = (pr.run(tp) - pr.run(tm)) / (2 * h)
+                errs.append(abs(fd - g[x]) / np.abs(g).max())
+            out["fd_check"] = {"entries": ent.tolist(), "h": h, "forward": "float64 library step",
+                               "max_abs_diff_over_max_grad": float(max(errs))}
+        pr.adjoint.close()
+        pr.lattice.close()
+        torch.cuda.empty_cache()
+    out["fp32_vs_fp64_grad_rel"] = float(np.abs(grads["fp32"] - grads["fp64"]).max() /
+                                         np.abs(grads["fp64"]).max())
+    return out
+
+
 def rel_err(a, b):
     return float(np.abs(a - b).max() / np.abs(b).max())
 
@@ -288,6 +359,7 @@ def main():
     ap.add_argument("--ladder-steps0", type=int, default=50,
                     help="steps of the coarsest ladder mesh (mesh k runs steps0 * 4^k)")
     ap.add_argument("--no-ladder", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--tile-cache", default=None, help="JSON cache of autotuned strip heights")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -393,6 +465,9 @@ def main():
     if not args.no_ladder:
         log(f"bench: refinement ladder, steps0 {args.ladder_steps0}")
         out["ladder"] = ladder_bench(args.ladder_steps0, tile_cache=args.tile_cache)
+    if not args.no_adjoint:
+        log("bench: adjoint 256x256, 500 steps")
+        out["adjoint"] = adjoint_bench()
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(case)

@@ -218,6 +218,34 @@ lbm_status lbm_fit_sigma(double a, double b, double R, double omega, double G, d
 lbm_status lbm_planar_gamma(double a, double b, double R, double omega, double G, double T,
                             double sigma, double* gamma0);
 
+/* ---- reverse mode: heater-profile gradient (Sec. 2 step, Sec. 4) --------
+ * Objective: evaporated liquid mass J = M_l(start) - M_l(end) over nsteps
+ * steps, M_l = sum_x rho H(rho), H(rho) = (1 + tanh((rho - rho_mid)/width))/2,
+ * rho the density a step reads (pull-streamed populations, Eq.
+ * DensityAndVelocityRelationToF).  Gradient with respect to the bottom-row
+ * Dirichlet temperatures t_bottom_val[x] (entries overridden by the side
+ * columns or not DIRICHLET get 0).
+ * Scope: periodic lattices (walls = 0) without gravity (gy = 0) with the
+ * energy equation on (thermal = 1); otherwise LBM_E_UNSUPPORTED.
+ * The forward pass runs the fused step on the context and stores a
+ * checkpoint every ckpt_every steps in dev_buf (caller-owned, 256-byte
+ * aligned, >= lbm_adjoint_bytes; it also holds ckpt_every recomputed states
+ * and the float64 adjoint fields).  The backward pass recomputes each
+ * segment with the same kernel (identical trajectory) and reverses it step
+ * by step; it leaves the context at the end state of the forward pass. */
+typedef struct lbm_adjoint lbm_adjoint;
+lbm_status lbm_adjoint_bytes(const lbm_params* p, int32_t nsteps, int32_t ckpt_every, size_t* bytes);
+lbm_status lbm_adjoint_create(lbm_ctx* ctx, int32_t nsteps, int32_t ckpt_every, double rho_mid, double width,
+                              void* dev_buf, size_t bytes, lbm_adjoint** out);
+void lbm_adjoint_destroy(lbm_adjoint* a);
+/* Advance ctx (initialised) by nsteps from its current state; J on the host. */
+lbm_status lbm_adjoint_forward(lbm_adjoint* a, double* J);
+/* grad_t_bottom (host, nx doubles) = dJ * dJ/dt_bottom_val.  Needs a
+ * forward pass first; may be called again for another dJ. */
+lbm_status lbm_adjoint_backward(lbm_adjoint* a, double dJ, double* grad_t_bottom);
+/* Host wall-clock milliseconds of the last forward and backward passes. */
+lbm_status lbm_adjoint_timing(const lbm_adjoint* a, double* forward_ms, double* backward_ms);
+
 /* One mesh of the refinement procedure (Sec. 3) relative to the base mesh
  * (dx = dx_mesh / dx_base, e.g. 1/2 for a twice finer mesh):
  *   a = a_base dx^2 (Eq. a-deltax), T = Tr T_c(a), Maxwell densities,

@@ -10,6 +10,8 @@ from ._native import (LBM_FP32_SHIFTED, LBM_FP64, T_ADIABATIC, T_DIRICHLET, T_FR
 from .sim import (Batch, Lattice, buffer_bytes, fit_sigma, make_params, planar_gamma,
                   pr_critical_temperature, pr_maxwell, refinement_level)
 
-__all__ = ["Lattice", "Batch", "refinement_level", "LbmParams", "LbmError", "make_params", "buffer_bytes", "lib",
+from .adjoint import HeaterAdjoint, HeaterProblem, evaporated_mass
+
+__all__ = ["HeaterAdjoint", "HeaterProblem", "evaporated_mass", "Lattice", "Batch", "refinement_level", "LbmParams", "LbmError", "make_params", "buffer_bytes", "lib",
            "pr_critical_temperature", "pr_maxwell", "fit_sigma", "planar_gamma",
            "LBM_FP64", "LBM_FP32_SHIFTED", "T_FREE", "T_DIRICHLET", "T_ADIABATIC"]

@@ -77,6 +77,13 @@ SIGNATURES = [
     ("lbm_batch_last_time", c_int32, [c_void_p, _DP, P(c_int64), P(c_int64)]),
     ("lbm_autotune_tile_y", c_int32, [c_void_p, P(c_int32), c_int32, c_int32, P(c_int32), _DP]),
     ("lbm_refinement_level", c_int32, [c_double] * 9 + [c_int64, P(LbmLevel)]),
+    ("lbm_adjoint_bytes", c_int32, [P(LbmParams), c_int32, c_int32, P(c_size_t)]),
+    ("lbm_adjoint_create", c_int32, [c_void_p, c_int32, c_int32, c_double, c_double, c_void_p, c_size_t,
+                                     P(c_void_p)]),
+    ("lbm_adjoint_destroy", None, [c_void_p]),
+    ("lbm_adjoint_forward", c_int32, [c_void_p, _DP]),
+    ("lbm_adjoint_backward", c_int32, [c_void_p, c_double, _DP]),
+    ("lbm_adjoint_timing", c_int32, [c_void_p, _DP, _DP]),
     ("lbm_kernel_times", c_int32, [c_void_p, _DP, P(c_int64)]),
     ("lbm_pr_critical_temperature", c_double, [c_double, c_double, c_double]),
     ("lbm_pr_maxwell", c_int32, [c_double, c_double, c_double, c_double, c_double, _DP, _DP, _DP]),

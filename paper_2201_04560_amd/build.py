@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB_NAME = "libpp2201_lbm.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
-SOURCES = ["lbm_step.hip", "lbm_aux.hip", "lbm_runtime.cpp", "lbm_batch.cpp", "lbm_params.cpp"]
+SOURCES = ["lbm_step.hip", "lbm_aux.hip", "lbm_runtime.cpp", "lbm_batch.cpp", "lbm_adjoint.hip", "lbm_params.cpp"]
 ARCH = os.environ.get("PP2201_ARCH", "gfx950")
 
 

@@ -79,3 +79,19 @@ def random_tiny(nx, ny, seed, walls=False, thermal=False, gy=0.0):
     uy = rng.uniform(-0.02, 0.02, (ny, nx))
     Tf = rng.uniform(0.85, 0.93, (ny, nx)) * eos.Tc
     return c, rho, ux, uy, Tf
+
+
+def heater_case(nx=16, ny=14, r=3.5, cy=5.0, seed=3, k=1.2):
+    """Droplet vaporisation inside a Dirichlet ring whose bottom row (the
+    heater profile) varies by +-1 % around 0.95 T_c; the droplet sits near
+    the heater.  Returns (case dict, rho, T, rho_mid, width)."""
+    eos, Tsat, rv, rl = coexistence()
+    Tout = 0.95 * eos.Tc
+    rng = np.random.default_rng(seed)
+    tb = Tout * (1.0 + 0.01 * rng.uniform(-1, 1, nx))
+    c = dict(nx=nx, ny=ny, a=2.0 / 49.0, sigma=0.1, kappa=0.1, rho_l=rl, rho_v=rv, thermal=True,
+             cv=6.0, lambda_l=2 / 3, lambda_v=2 / 3, t_side_dirichlet=True, t_side_val=Tout,
+             t_bottom_kind=np.full(nx, T_DIRICHLET), t_bottom_val=tb,
+             t_top_kind=np.full(nx, T_DIRICHLET), t_top_val=np.full(nx, Tout), **wl.DROPLET_RATES)
+    rho, T = wl.droplet(nx, ny, r, k, rl, rv, Tsat, Tout, centre=(nx / 2, cy), seed=seed)
+    return c, rho, T, 0.5 * (rl + rv), (rl - rv) / 8.0

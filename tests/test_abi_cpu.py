@@ -152,3 +152,19 @@ def test_pool_ladder_levels(lib):
         assert abs(tb[h0] / lv["Tc"] - 0.95) < 1e-14 and abs(tb[0] / lv["Tc"] - 0.86) < 1e-14
         assert p.precision == 1 and p.walls == 1 and p.thermal == 1
         assert abs(p.rho_v - base["params"].rho_v) < 1e-10
+
+
+def test_adjoint_bytes_and_scope(lib):
+    import ctypes
+
+    import paper_2201_04560_amd as pp
+
+    p = pp.make_params(256, 256, thermal=1, precision=1)
+    n1, n2 = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.lbm_adjoint_bytes(ctypes.byref(p), 500, 50, ctypes.byref(n1)) == 0
+    assert lib.lbm_adjoint_bytes(ctypes.byref(p), 1000, 50, ctypes.byref(n2)) == 0
+    assert n2.value > n1.value > 61 * 256 * 256 * 10 * 4  # 10 + 50 + 1 float32 states
+    for kw in (dict(walls=1), dict(gy=-1e-5), dict(thermal=0)):
+        q = pp.make_params(64, 64, **{**dict(thermal=1), **kw})
+        assert lib.lbm_adjoint_bytes(ctypes.byref(q), 10, 5, ctypes.byref(n1)) == 6
+    assert lib.lbm_adjoint_bytes(ctypes.byref(p), 0, 5, ctypes.byref(n1)) == 1

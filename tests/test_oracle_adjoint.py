@@ -4,29 +4,14 @@ heater value is overridden, linearity of the directional derivative."""
 import numpy as np
 import pytest
 
-import workloads as wl
+import cases
 from oracle import adjoint as adj
-from oracle import thermo as th
-from oracle.step import Params
-
-DIRICHLET = 1
 
 
 def tiny_case(nx=16, ny=14, nsteps=12, seed=3):
     """Droplet near a heated bottom row inside a Dirichlet ring."""
-    eos = th.EOS(2.0 / 49.0)
-    Tsat = 0.86 * eos.Tc
-    rv, rl, _ = th.maxwell(eos, Tsat)
-    Tout = 0.95 * eos.Tc
-    rng = np.random.default_rng(seed)
-    tb = Tout * (1.0 + 0.01 * rng.uniform(-1, 1, nx))
-    p = Params(nx=nx, ny=ny, a=2.0 / 49.0, sigma=0.1, kappa=0.1, rho_l=rl, rho_v=rv, thermal=True,
-               cv=6.0, lambda_l=2 / 3, lambda_v=2 / 3, t_side_dirichlet=True, t_side_val=Tout,
-               t_bottom_kind=np.full(nx, DIRICHLET), t_bottom_val=tb,
-               t_top_kind=np.full(nx, DIRICHLET), t_top_val=np.full(nx, Tout),
-               **wl.DROPLET_RATES)
-    rho, T = wl.droplet(nx, ny, 3.5, 1.2, rl, rv, Tsat, Tout, centre=(nx / 2, 5.0), seed=seed)
-    return p, rho, T, nsteps, 0.5 * (rl + rv), (rl - rv) / 8.0
+    c, rho, T, rm, w = cases.heater_case(nx, ny, seed=seed)
+    return cases.oracle_params(c), rho, T, nsteps, rm, w
 
 
 def test_complex_step_matches_central_differences():
