@@ -84,7 +84,12 @@ def pool_case(nx=4096, ny=4096):
     return nx, ny, kw, bnd, rho, T
 
 
-def run_lattice(case, precision, warmup, steps, want_fields=True, tile_y=0):
+def run_lattice(case, precision, warmup, steps, want_fields=True, tile_y=0, tune=None):
+    """Warm up, then time `steps` launches of the step kernel: host wall
+    clock around the whole region, and one pair of HIP events recorded on the
+    lattice's stream around the same launches (their mean is the kernel's
+    average launch duration, inter-launch gaps included).  tile_y = 0 with a
+    TileCache picks the strip height with the library's autotuner."""
     import torch
 
     from paper_2201_04560_amd import Lattice, make_params
@@ -93,20 +98,19 @@ def run_lattice(case, precision, warmup, steps, want_fields=True, tile_y=0):
     lat = Lattice(make_params(nx, ny, precision=precision, tile_y=tile_y, **kw))
     lat.set_boundary(**bnd)
     lat.init_fields(rho, None, None, T)
+    if tile_y == 0 and tune is not None:
+        tune.tune(lat, device=torch.cuda.get_device_name(0))
     if warmup:
         lat.step(warmup)
     lat.sync()
     torch.cuda.synchronize()
-    lat.kernel_timing(True)
     t0 = time.perf_counter()
     lat.step(steps)
     lat.sync()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ksum, kcnt = lat.kernel_times()
-    lat.kernel_timing(False)
-    out = dict(wall_s=t1 - t0, ev_ms=lat.last_step_ms(), kernel_ms_avg=ksum / max(kcnt, 1),
-               launches=kcnt)
+    ev = lat.last_step_ms()
+    out = dict(wall_s=t1 - t0, ev_ms=ev, kernel_ms_avg=ev / steps, launches=steps, tile_y=lat.tile_y)
     if want_fields:
         out["fields"] = lat.fields()
         out["norms"] = lat.norms()
@@ -361,6 +365,8 @@ def main():
     ap.add_argument("--no-ladder", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--tile-cache", default=None, help="JSON cache of autotuned strip heights")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="library default strip heights instead of the autotuner")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -372,13 +378,16 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     from paper_2201_04560_amd import LBM_FP32_SHIFTED, LBM_FP64
+    from paper_2201_04560_amd.ladder import TileCache
+
+    tune = None if (args.tile_y or args.no_autotune) else TileCache(args.tile_cache)
 
     if args.profile_case:
         pcase = vaporisation_case() if args.profile_case == "vaporisation512" else pool_case()
         for name, prec in (("fp32", LBM_FP32_SHIFTED), ("fp64", LBM_FP64)):
             if args.only in (name, "both"):
                 r = run_lattice(pcase, prec, args.warmup, args.steps, want_fields=False,
-                                tile_y=args.tile_y)
+                                tile_y=args.tile_y, tune=tune)
                 log(f"profile: {args.profile_case} {name} kernel {r['kernel_ms_avg'] * 1e3:.2f} us "
                     f"avg over {r['launches']} launches")
         if args.copy_mib > 0:
@@ -399,10 +408,11 @@ def main():
         if args.only not in (name, "both"):
             continue
         log(f"bench: {name} {nx}x{ny} vaporisation, warmup {args.warmup}, steps {args.steps}")
-        res[name] = run_lattice(case, prec, args.warmup, args.steps, tile_y=args.tile_y)
+        res[name] = run_lattice(case, prec, args.warmup, args.steps, tile_y=args.tile_y, tune=tune)
         r = res[name]
         log(f"bench: {name} {args.steps * nodes / r['wall_s'] / 1e6:.0f} MLUPS, kernel "
-            f"{r['kernel_ms_avg'] * 1e3:.2f} us avg over {r['launches']} launches")
+            f"{r['kernel_ms_avg'] * 1e3:.2f} us avg over {r['launches']} launches, "
+            f"tile_y {r['tile_y']}")
 
     main_name = "fp32" if "fp32" in res else "fp64"
     m = res[main_name]
@@ -424,7 +434,8 @@ def main():
                                "in vapour held at 0.95 Tc, sigma=kappa=0.1, cv=6, lambda=2/3, no "
                                "gravity, seed 0 (+-0.5 interface jitter)",
                    "nx": nx, "ny": ny, "storage": "f32 shifted populations (f - w rho_v) + f32 T; "
-                   "f64 EOS/psi/forces and reductions", "steps_total": args.warmup + args.steps},
+                   "f64 EOS/psi/forces and reductions", "steps_total": args.warmup + args.steps,
+                   "tile_y": m["tile_y"]},
         "roofline": roofline(main_name == "fp32", nodes, m["kernel_ms_avg"],
                              measured_traffic(f"vaporisation512_{main_name}")),
     }
@@ -434,6 +445,7 @@ def main():
         r64, _, _, T64 = f64["fields"]
         out["fp64_plain"] = {
             "value": round(args.steps * nodes / f64["wall_s"] / 1e6, 1), "unit": "MLUPS",
+            "tile_y": f64["tile_y"],
             "ms_per_step": round(f64["wall_s"] * 1e3 / args.steps, 5),
             "roofline": roofline(False, nodes, f64["kernel_ms_avg"],
                                  measured_traffic("vaporisation512_fp64")),
@@ -453,10 +465,11 @@ def main():
             if args.only not in (name, "both"):
                 continue
             log(f"bench: sizing {name} {pc[0]}x{pc[1]} pool, {args.sizing_steps} steps")
-            r = run_lattice(pc, prec, 20, args.sizing_steps, want_fields=False)
+            r = run_lattice(pc, prec, 20, args.sizing_steps, want_fields=False, tune=tune)
             n2 = pc[0] * pc[1]
             sz[name] = {"value": round(args.sizing_steps * n2 / r["wall_s"] / 1e6, 1),
                         "unit": "MLUPS",
+                        "tile_y": r["tile_y"],
                         "roofline": roofline(name == "fp32", n2, r["kernel_ms_avg"],
                                              measured_traffic(f"pool4096_{name}"))}
         out["hbm_sized_run"] = {"workload": "pool boiling physics 4096x4096 (walls, heater, "

@@ -23,16 +23,22 @@ constexpr int kNormBlocks = 512;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-int default_tile_y(int nx, int ny, int walls) {
-  // aim at ~8 one-wave workgroups per CU; small lattices get short strips
-  // (the step is then bound by one wave's per-row latency), large ones long
-  // strips (less recomputation of the 6 halo rows)
+int default_tile_y(int nx, int ny, int walls, int fp32) {
+  // The longest strip that still gives every SIMD about two one-wave
+  // workgroups (float64: one and a half): long strips recompute fewer of
+  // the 6 halo rows, but a lattice too small for that runs at the shortest
+  // strips, where the step is bound by one wave's per-row latency (measured
+  // on MI355X: 512^2 -> 3 rows (float32) / 5 rows (float64), 4096^2 -> 64).
   const int ntx = (nx + tile_x(walls) - 1) / tile_x(walls);
-  const int target = 8192;
-  const int nty = std::max(1, (target + ntx - 1) / ntx);
-  int ty = (ny + nty - 1) / nty;
-  ty = std::max(ty, 4);
-  ty = std::min(ty, 256);
+  const int want = fp32 ? 2048 : 1536;
+  static const int cand[] = {64, 48, 32, 24, 16, 12, 8, 6, 5, 4, 3};
+  int ty = fp32 ? 3 : 5;
+  for (int c : cand) {
+    if (static_cast<long long>(ntx) * ((ny + c - 1) / c) >= want) {
+      ty = c;
+      break;
+    }
+  }
   return std::max(2, std::min(ty, std::max(ny, 2)));
 }
 
@@ -45,7 +51,7 @@ void lbm::make_layout(const lbm_params& p, Layout& L) {
   // do not all land in one HBM channel
   const long long cells = (long long)L.pitch * p.ny;
   L.plane = (long long)align_up(size_t(cells), 256) + 192;
-  L.ty = p.tile_y > 0 ? p.tile_y : default_tile_y(p.nx, p.ny, p.walls);
+  L.ty = p.tile_y > 0 ? p.tile_y : default_tile_y(p.nx, p.ny, p.walls, p.precision == LBM_FP32_SHIFTED);
   L.ntx = (p.nx + tile_x(p.walls) - 1) / tile_x(p.walls);
   L.nty = (p.ny + L.ty - 1) / L.ty;
   L.nblocks = L.ntx * L.nty;

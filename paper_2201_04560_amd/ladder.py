@@ -76,7 +76,8 @@ class TileCache:
         e = self.table.get(self.key(p, device))
         return None if e is None else int(e["tile_y"])
 
-    def tune(self, lattice, candidates=(2, 3, 4, 6, 8, 12, 16, 24, 32), steps=20, device=""):
+    def tune(self, lattice, candidates=(2, 3, 4, 5, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128), steps=20,
+             device=""):
         """Cached strip height for this lattice, autotuning (and storing) it on
         a miss; the lattice's tile_y is set either way.  Returns tile_y."""
         ty = self.lookup(lattice.p, device)
