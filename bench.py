@@ -30,7 +30,6 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2201_04560_amd", "csrc", "lbm_step.hip")
 
 
 def log(*a):
@@ -84,6 +83,14 @@ def pool_case(nx=4096, ny=4096):
     return nx, ny, kw, bnd, rho, T
 
 
+def device_key():
+    """Architecture and compute-unit count of GPU 0 (the tile cache key)."""
+    import torch
+
+    pr = torch.cuda.get_device_properties(0)
+    return f"{pr.gcnArchName.split(':')[0]}/{pr.multi_processor_count}CU"
+
+
 def run_lattice(case, precision, warmup, steps, want_fields=True, tile_y=0, tune=None):
     """Warm up, then time `steps` launches of the step kernel: host wall
     clock around the whole region, and one pair of HIP events recorded on the
@@ -99,7 +106,7 @@ def run_lattice(case, precision, warmup, steps, want_fields=True, tile_y=0, tune
     lat.set_boundary(**bnd)
     lat.init_fields(rho, None, None, T)
     if tile_y == 0 and tune is not None:
-        tune.tune(lat, device=torch.cuda.get_device_name(0))
+        tune.tune(lat, device=device_key())
     if warmup:
         lat.step(warmup)
     lat.sync()
@@ -128,16 +135,20 @@ def roofline(fp32, nodes, kernel_ms, traffic):
             "alg_bytes_per_launch": b, "kernel_ms_avg": round(kernel_ms, 5)}
 
 
-def measured_traffic(key):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, valid
-    only while the kernel source is the one they were taken on."""
+def measured_traffic(key, tile_y):
+    """HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a
+    copy kernel of known size) from the committed counter summary, valid only
+    for the kernel sources and the strip height they were taken on."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
-        h = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-        if t.get("kernel_sha256") != h:
+        h = hashlib.sha256()
+        for f in t.get("kernel_sources", []):
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+        if not t.get("kernel_sources") or t.get("kernel_sha256") != h.hexdigest():
             return None
-        return t.get("per_launch_bytes", {}).get(key)
+        return t.get("per_launch_bytes", {}).get(key, {}).get(str(tile_y))
     except (OSError, ValueError):
         return None
 
@@ -200,7 +211,7 @@ def ladder_bench(steps0, levels=(0, 1, 2, 3), seeds=(0, 1, 2, 3), tile_cache=Non
     from paper_2201_04560_amd.ladder import TileCache
 
     cache = TileCache(tile_cache)
-    dev = torch.cuda.get_device_name(0)
+    dev = device_key()
     specs = [(k, sd) for k in levels for sd in seeds]
 
     def build(precision):
@@ -437,7 +448,7 @@ def main():
                    "f64 EOS/psi/forces and reductions", "steps_total": args.warmup + args.steps,
                    "tile_y": m["tile_y"]},
         "roofline": roofline(main_name == "fp32", nodes, m["kernel_ms_avg"],
-                             measured_traffic(f"vaporisation512_{main_name}")),
+                             measured_traffic(f"vaporisation512_{main_name}", m["tile_y"])),
     }
     if "fp32" in res and "fp64" in res:
         f32, f64 = res["fp32"], res["fp64"]
@@ -448,7 +459,7 @@ def main():
             "tile_y": f64["tile_y"],
             "ms_per_step": round(f64["wall_s"] * 1e3 / args.steps, 5),
             "roofline": roofline(False, nodes, f64["kernel_ms_avg"],
-                                 measured_traffic("vaporisation512_fp64")),
+                                 measured_traffic("vaporisation512_fp64", f64["tile_y"])),
         }
         out["speedup_fp32_vs_fp64"] = round(f64["wall_s"] / f32["wall_s"], 3)
         out["fp32_error_vs_fp64"] = {
@@ -471,7 +482,7 @@ def main():
                         "unit": "MLUPS",
                         "tile_y": r["tile_y"],
                         "roofline": roofline(name == "fp32", n2, r["kernel_ms_avg"],
-                                             measured_traffic(f"pool4096_{name}"))}
+                                             measured_traffic(f"pool4096_{name}", r["tile_y"]))}
         out["hbm_sized_run"] = {"workload": "pool boiling physics 4096x4096 (walls, heater, "
                                             "gravity, thermal), 1.3 GB f32 / 2.7 GB f64 state",
                                 **sz}

@@ -185,6 +185,12 @@ __device__ __forceinline__ int pmod(int a, int n) {
   return r < 0 ? r + n : r;
 }
 
+// a modulo n for a in [-3, n + 3): one compare-and-add unless n < 3
+__device__ __forceinline__ int wrap3(int a, int n) {
+  if (n < 3) return pmod(a, n);
+  return a < 0 ? a + n : (a >= n ? a - n : a);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kLanes);

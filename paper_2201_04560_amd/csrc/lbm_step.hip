@@ -125,14 +125,25 @@ struct WavesPerEU {
   static constexpr int value = sizeof(S) == 4 ? 3 : 2;
 };
 
-// ring slot of row r - delta when row r sits in slot ph (rings of 4 rows)
-__device__ constexpr int sl(int ph, int delta) { return (ph - delta) & 3; }
+// compile-time loop: f(integral_constant<int, j>) for j = 0 .. N-1
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 template <int N>
 using Ph = std::integral_constant<int, N>;
 
-// one strip of one lattice; bid is the workgroup's index within its lattice
-template <class S, class C, bool WALLS, bool THERMAL, int MODE>
+// one strip of one lattice; bid is the workgroup's index within its lattice.
+// RPI rows enter the pipeline per iteration.  The code is written for any
+// RPI; 1 is instantiated: with 2 (two independent row chains per wave) the
+// step ran 3-6 % slower on 512^2 and up to 60 % slower on 4096^2 on MI355X
+// (more registers, no gain in overlap).
+template <class S, class C, bool WALLS, bool THERMAL, int MODE, int RPI>
 __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroOut& O, const int bid) {
   const int lane = threadIdx.x;
   const int nb = A.ntx * A.nty;
@@ -167,13 +178,18 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
   auto ld = [](const char* base, uint32_t off) { return *reinterpret_cast<const S*>(base + off); };
   auto st = [](char* base, uint32_t off, S v) { *reinterpret_cast<S*>(base + off) = v; };
 
-  // rings of 4 rows; row r - delta of iteration k lives in slot sl(k & 3, delta)
-  __shared__ double s_rho[4][kLanes];
-  __shared__ double s_psi[4][kLanes];
-  __shared__ C s_T[4][kLanes];
-  __shared__ C s_ux[4][kLanes];
-  __shared__ C s_uy[4][kLanes];
-  __shared__ C s_Ts[4][kLanes];
+  // rings of R rows indexed by (row - first row) & (R - 1)
+  constexpr int R = 4 * RPI;  // ring rows
+  __shared__ double s_rho[R][kLanes];
+  __shared__ double s_psi[R][kLanes];
+  __shared__ C s_T[R][kLanes];
+  __shared__ C s_ux[R][kLanes];
+  __shared__ C s_uy[R][kLanes];
+  __shared__ C s_Ts[R][kLanes];
+  // density in the compute type for the energy stencils (float32 path only;
+  // the float64 path reads s_rho)
+  constexpr bool kRhoC = sizeof(C) < sizeof(double);
+  __shared__ C s_rc[kRhoC ? R : 1][kLanes];
 
   // mean density of the current state (Eq. gravitational_force): the
   // partials are summed in the same order by every workgroup
@@ -189,7 +205,7 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
   auto load_row = [&](int r, C (&gn)[9], C& Tn) {
     const bool have = WALLS ? (r >= 0 && r < ny) : true;
     if (!have) return;
-    const int yr = __builtin_amdgcn_readfirstlane(WALLS ? r : pmod(r, ny));
+    const int yr = __builtin_amdgcn_readfirstlane(WALLS ? r : wrap3(r, ny));
     int ydn, yup;
     bool kdn = true, kup = true;
     if (WALLS) {
@@ -223,20 +239,31 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
 
   uint32_t err = 0;
   double mass_acc = 0.0;
-  C gn[9], Tn = C(0);
+  const int rbase = y0 - kHaloY;                 // first row of stage A
+  const int nit = (y1 - y0) + 2 * kHaloY;        // rows through stage A
+  const int rend = rbase + nit;                  // one past the last of them
+  // ring slot of a row: (row - rbase) & (R - 1); in iteration k the j-th
+  // row has slot (RPI k + j) & (R - 1), a constant once k & 3 is fixed
+  C gn[RPI][9], Tn[RPI];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) gn[i] = C(0);
-  load_row(y0 - kHaloY, gn, Tn);
-  C gp[9];  // pulled populations of row r-1 (for its collision)
+  for (int j = 0; j < RPI; ++j) {
+    Tn[j] = C(0);
 #pragma unroll
-  for (int i = 0; i < 9; ++i) gp[i] = C(0);
-  C jxp = C(0), jyp = C(0);
+    for (int i = 0; i < 9; ++i) gn[j][i] = C(0);
+    if (rbase + j < rend) load_row(rbase + j, gn[j], Tn[j]);
+  }
+  // carries from the previous iteration's last row (its pulled populations
+  // and moments feed the next row's collision)
+  C gprev[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) gprev[i] = C(0);
+  C jxprev = C(0), jyprev = C(0);
   double psiw_b = 0.0, psiw_t = 0.0;
-  // per-lane carries of the energy stages: EOS terms of rows r-1, r-2 and
-  // 1/rho of row r-2 (from stage B), stage-C coefficients for stage D
-  C a1_1 = C(0), a2_1 = C(0), a1_2 = C(0), a2_2 = C(0), irho_1 = C(0);
-  EnergyCoef<C> ec_prev{};
-  const int nit = (y1 - y0) + 2 * kHaloY;
+  // rolling per-row carries: EOS terms of the last two stage-A rows (for
+  // stage C two rows later), 1/rho of the last stage-B row and the energy
+  // coefficients of the last stage-C row (each read one row later)
+  C a1h[2] = {C(0), C(0)}, a2h[2] = {C(0), C(0)}, irprev = C(0);
+  EnergyCoef<C> ecprev{};
 
   // kind of the temperature condition at (y, x') for the lane's column x'
   // (xs = 0, 1, 2 for x - 1, x, x + 1); only evaluated on rows 0 / ny - 1
@@ -260,357 +287,426 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
     return int(T_FREE);
   };
 
-  auto body = [&](auto phc, const int k) {
-    constexpr int PH = decltype(phc)::value;
-    const int r = y0 - kHaloY + k;
-    // --------------------------------------------------------- stage A(r)
-    C g[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) g[i] = gn[i];
-    const C Tr = Tn;
-    if (k + 1 < nit) load_row(r + 1, gn, Tn);
-    C jx = C(0), jy = C(0), a1 = C(0), a2 = C(0);
-    {
-      const bool have = WALLS ? (r >= 0 && r < ny) : true;
-      if (have) {
-        const int yr = WALLS ? r : pmod(r, ny);
-        const double T = double(Tr);
-        double rho, psi = 0.0;
-        if (WALLS && (yr == 0 || yr == ny - 1)) {
-          // known part of the wall density; closed once psi of the
-          // neighbour row exists
-          const C gk = (yr == 0) ? g[0] + g[1] + g[3] + C(2) * (g[4] + g[7] + g[8])
-                                 : g[0] + g[1] + g[3] + C(2) * (g[2] + g[5] + g[6]);
-          rho = rref + double(gk);
-        } else {
-          C sg = g[0];
-#pragma unroll
-          for (int i = 1; i < 9; ++i) sg += g[i];
-          jx = g[1] - g[3] + g[5] - g[6] - g[7] + g[8];
-          jy = g[2] - g[4] + g[5] + g[6] - g[7] - g[8];
-          rho = rref + double(sg);
-          const EosNode e = eos_node(rho, T, P);
-          psi = psi_fast(rho, T, e, P, err);
-          a1 = C(e.A1);
-          a2 = C(e.A2);
-        }
-        s_rho[sl(PH, 0)][lane] = rho;
-        s_psi[sl(PH, 0)][lane] = psi;
-        s_T[sl(PH, 0)][lane] = Tr;
+  // ------------------------------------------------------------ stage A(r)
+  // moments, EOS and psi of row r (slot SA); wall rows keep the known part
+  // of their density until the closure
+  auto stageA = [&](auto sa, const int r, C (&g)[9], const C Tr, C& jx, C& jy, C& a1, C& a2) {
+    constexpr int SA = decltype(sa)::value;
+    jx = C(0);
+    jy = C(0);
+    a1 = C(0);
+    a2 = C(0);
+    const bool have = WALLS ? (r >= 0 && r < ny) : true;
+    if (have) {
+      const int yr = WALLS ? r : wrap3(r, ny);
+      const double T = double(Tr);
+      double rho, psi = 0.0;
+      if (WALLS && (yr == 0 || yr == ny - 1)) {
+        const C gk = (yr == 0) ? g[0] + g[1] + g[3] + C(2) * (g[4] + g[7] + g[8])
+                               : g[0] + g[1] + g[3] + C(2) * (g[2] + g[5] + g[6]);
+        rho = rref + double(gk);
       } else {
+        C sg = g[0];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) g[i] = C(0);
+        for (int i = 1; i < 9; ++i) sg += g[i];
+        jx = g[1] - g[3] + g[5] - g[6] - g[7] + g[8];
+        jy = g[2] - g[4] + g[5] + g[6] - g[7] - g[8];
+        rho = rref + double(sg);
+        const EosNode e = eos_node(rho, T, P);
+        psi = psi_fast(rho, T, e, P, err);
+        a1 = C(e.A1);
+        a2 = C(e.A2);
       }
+      s_rho[SA][lane] = rho;
+      if constexpr (kRhoC) s_rc[SA][lane] = C(rho);
+      s_psi[SA][lane] = psi;
+      s_T[SA][lane] = Tr;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) g[i] = C(0);
     }
-    stage_barrier();
-
-    // ------------------------------------------------------ wall closures
-    if (WALLS) {
-      const bool cb = (r == 1) && (0 >= y0 - kHaloY);
-      const bool ct = (r == ny - 1) && (ny - 2 >= y0 - kHaloY);
-      if (cb || ct) {
-        // bottom: wall row r - 1, neighbour row r; top: wall row r, neighbour r - 1
-        const int sw = cb ? sl(PH, 1) : sl(PH, 0), sa = cb ? sl(PH, 0) : sl(PH, 1);
-        const double sgn = cb ? 1.0 : -1.0;
-        const double K = s_rho[sw][lane];
-        const double Tw = double(s_T[sw][lane]);
-        const double rw = A.tabd[(cb ? 0 : 1) * nx + x];
-        const double psiw = psi_checked(rw, Tw, P, err);
-        const double B = wall_coef_B(s_psi[sa][lane], s_psi[sa][lp], s_psi[sa][lm], psiw, sgn, P);
-        const double rwall = wall_density(K, B, Tw, sgn, P);
-        s_rho[sw][lane] = rwall;
-        s_psi[sw][lane] = psi_checked(rwall, Tw, P, err);
-        if (cb) psiw_b = psiw; else psiw_t = psiw;
-      }
-      stage_barrier();
-    }
-
-    // ------------------------------------------------------- stage B(r-1)
-    C irho_new = C(0);
-    if (k >= 2) {
-      const int s = r - 1;
-      const bool have = WALLS ? (s >= 0 && s < ny) : true;
-      if (have) {
-        const int ys = WALLS ? s : pmod(s, ny);
-        constexpr int km = sl(PH, 2), kc = sl(PH, 1), kq = sl(PH, 0);  // rows s-1, s, s+1
-        const bool wb = WALLS && ys == 0, wt = WALLS && ys == ny - 1;
-        const double pc = s_psi[kc][lane];
-        const double p1 = s_psi[kc][lp], p3 = s_psi[kc][lm];
-        double p2, p5, p6, p4, p7, p8;
-        if (wt) {
-          p2 = p5 = p6 = psiw_t;
-        } else {
-          p2 = s_psi[kq][lane];
-          p5 = s_psi[kq][lp];
-          p6 = s_psi[kq][lm];
-        }
-        if (wb) {
-          p4 = p7 = p8 = psiw_b;
-        } else {
-          p4 = s_psi[km][lane];
-          p7 = s_psi[km][lm];
-          p8 = s_psi[km][lp];
-        }
-        const double rho = s_rho[kc][lane];
-        const double G = P.G;
-        // Eq. shanchen (psi_w for solid neighbours: Eq. shanchen-walls)
-        const double d1 = p1 - pc, d2 = p2 - pc, d3 = p3 - pc, d4 = p4 - pc;
-        const double d5 = p5 - pc, d6 = p6 - pc, d7 = p7 - pc, d8 = p8 - pc;
-        const double sx = (1.0 / 3.0) * (p1 - p3) + (1.0 / 12.0) * ((p5 - p7) + (p8 - p6));
-        const double sy = (1.0 / 3.0) * (p2 - p4) + (1.0 / 12.0) * ((p5 - p7) + (p6 - p8));
-        const double fmx = -G * pc * sx;
-        const double fmy = -G * pc * sy;
-        const double fx = fmx;
-        const double fy = fmy + P.gy * (rho - rho_bar);
-        // Eq. Q / Q-psi-based
-        const double kq2 = P.kappa * G * 0.5 * pc;
-        const double dsum = (d5 + d6) + (d7 + d8);
-        const double qxx = kq2 * ((1.0 / 3.0) * (d1 + d3) + (1.0 / 12.0) * dsum);
-        const double qyy = kq2 * ((1.0 / 3.0) * (d2 + d4) + (1.0 / 12.0) * dsum);
-        const double qxy = kq2 * ((1.0 / 12.0) * ((d5 + d7) - (d6 + d8)));
-
-        C jxs = jxp, jys = jyp;
-        if (wb || wt) {
-          // Zou-He reconstruction for the prescribed momentum -F^m/2
-          jxs = C(-0.5 * fmx);
-          jys = C(-0.5 * fmy);
-          const C d = C(0.5) * (gp[1] - gp[3]);
-          if (wb) {
-            gp[2] = gp[4] + C(2.0 / 3.0) * jys;
-            gp[5] = gp[7] - d + C(0.5) * jxs + jys * C(1.0 / 6.0);
-            gp[6] = gp[8] + d - C(0.5) * jxs + jys * C(1.0 / 6.0);
-          } else {
-            gp[4] = gp[2] - C(2.0 / 3.0) * jys;
-            gp[7] = gp[5] + d - C(0.5) * jxs - jys * C(1.0 / 6.0);
-            gp[8] = gp[6] - d + C(0.5) * jxs - jys * C(1.0 / 6.0);
-          }
-        }
-        const double inv_rho = rcp64(rho);
-        irho_new = C(inv_rho);
-        const double uxd = (double(jxs) + 0.5 * fx) * inv_rho;
-        const double uyd = (double(jys) + 0.5 * fy) * inv_rho;
-        s_ux[kc][lane] = C(uxd);
-        s_uy[kc][lane] = C(uyd);
-
-        const bool inseg = s >= y0 && s < y1 && outlane;
-        if (MODE == MODE_STEP && inseg) {
-          // ---- MRT collision in shifted moments n = M g (g = f - w rho_ref)
-          const C ux = C(uxd), uy = C(uyd), Fx = C(fx), Fy = C(fy), rc = C(rho);
-          const C sg = C(rho - rref);
-          const C a4 = (gp[1] + gp[2]) + (gp[3] + gp[4]);
-          const C d4s = (gp[5] + gp[6]) + (gp[7] + gp[8]);
-          const C n1 = C(-4) * gp[0] - a4 + C(2) * d4s;
-          const C n2 = C(4) * gp[0] - C(2) * a4 + d4s;
-          const C n4 = C(2) * (gp[3] - gp[1]) + (gp[5] - gp[7]) + (gp[8] - gp[6]);
-          const C n6 = C(2) * (gp[4] - gp[2]) + (gp[5] - gp[7]) + (gp[6] - gp[8]);
-          const C n7 = (gp[1] + gp[3]) - (gp[2] + gp[4]);
-          const C n8 = (gp[5] + gp[7]) - (gp[6] + gp[8]);
-          const C u2 = ux * ux + uy * uy;
-          const C uF = ux * Fx + uy * Fy;
-          // sigma term 12 sigma |F^m|^2 / (psi^2 (tau - 1/2))
-          const C fm2_ps2 = C((fmx * fmx + fmy * fmy) * rcp64(pc * pc));
-          const C te = C(P.sig_e) * fm2_ps2, tz = C(P.sig_z) * fm2_ps2;
-          C snu = Q.snu_const;
-          if (Q.snu_varies) {
-            const C eta = Q.eta_v + (Q.eta_l - Q.eta_v) * (rc - Q.rho_v) * Q.inv_drho;
-            snu = rcp_c(C(3) * eta + C(0.5));
-          }
-          const C se = Q.s_e, sz = Q.s_z, sq = Q.s_q;
-          const C qs = C(qxx + qyy), qd = C(qxx - qyy);
-          const C r3u2 = C(3) * rc * u2;
-          const C m0 = sg;
-          const C m1 = n1 - se * (n1 + C(2) * sg - r3u2) + (C(1) - se * C(0.5)) * (C(6) * uF + te) +
-                       C(1.5) * se * qs;
-          const C m2 = n2 - sz * (n2 - sg + r3u2) - (C(1) - sz * C(0.5)) * (C(6) * uF + tz) -
-                       C(1.5) * sz * qs;
-          const C m3 = jxs + Fx;
-          const C m4 = n4 - sq * (n4 + rc * ux) - (C(1) - sq * C(0.5)) * Fx;
-          const C m5 = jys + Fy;
-          const C m6 = n6 - sq * (n6 + rc * uy) - (C(1) - sq * C(0.5)) * Fy;
-          const C hnu = C(1) - snu * C(0.5);
-          const C m7 = n7 - snu * (n7 - rc * (ux * ux - uy * uy)) + hnu * C(2) * (ux * Fx - uy * Fy) -
-                       snu * qd;
-          const C m8 = n8 - snu * (n8 - rc * ux * uy) + hnu * (ux * Fy + uy * Fx) - snu * C(qxy);
-          // f* = M^-1 m*
-          const C a0 = m0 * C(1.0 / 9.0);
-          const C ax0 = a0 - m1 * C(1.0 / 36.0) - m2 * C(1.0 / 18.0);
-          const C dg0 = a0 + m1 * C(1.0 / 18.0) + m2 * C(1.0 / 36.0);
-          const C j3 = m3 * C(1.0 / 6.0), j5 = m5 * C(1.0 / 6.0);
-          const C q4 = m4 * C(1.0 / 6.0), q6 = m6 * C(1.0 / 6.0);
-          const C q4h = m4 * C(1.0 / 12.0), q6h = m6 * C(1.0 / 12.0);
-          const C p7 = m7 * C(0.25), p8 = m8 * C(0.25);
-          C o[9];
-          o[0] = a0 + (m2 - m1) * C(1.0 / 9.0);
-          o[1] = ax0 + j3 - q4 + p7;
-          o[2] = ax0 + j5 - q6 - p7;
-          o[3] = ax0 - j3 + q4 + p7;
-          o[4] = ax0 - j5 + q6 - p7;
-          o[5] = dg0 + j3 + j5 + q4h + q6h + p8;
-          o[6] = dg0 - j3 + j5 - q4h + q6h - p8;
-          o[7] = dg0 - j3 - j5 - q4h - q6h + p8;
-          o[8] = dg0 + j3 - j5 + q4h - q6h - p8;
-          char* orow = fout + size_t(__builtin_amdgcn_readfirstlane(ys)) * row_b;
-#pragma unroll
-          for (int i = 0; i < 9; ++i) st(orow + i * plane_b, ox, S(o[i]));
-          if (A.want_mass) {
-            // known-part density of the next step (walls: the populations
-            // leaving through a wall are replaced by those the closure will
-            // rebuild from the neighbour row)
-            double m = rref;
-#pragma unroll
-            for (int i = 0; i < 9; ++i) m += double(S(o[i]));
-            if (WALLS) {
-              const double dn = double(S(o[4])) + double(S(o[7])) + double(S(o[8])) + rref / 6.0;
-              const double up = double(S(o[2])) + double(S(o[5])) + double(S(o[6])) + rref / 6.0;
-              if (ys == 0) m -= dn;
-              if (ys == 1) m += dn;
-              if (ys == ny - 2) m += up;
-              if (ys == ny - 1) m -= up;
-            }
-            mass_acc += m;
-          }
-        }
-        if (MODE == MODE_MACRO && inseg) {
-          const long long id = (long long)ys * nx + x;
-          if (O.rho) O.rho[id] = rho;
-          if (O.ux) O.ux[id] = uxd;
-          if (O.uy) O.uy[id] = uyd;
-          if (O.T) O.T[id] = double(s_T[kc][lane]);
-          if (O.f) {
-            const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
-                                 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
-            const long long N = (long long)nx * ny;
-            for (int i = O.f_first; i < O.f_first + O.f_count; ++i)
-              O.f[(long long)(i - O.f_first) * N + id] = double(gp[i]) + w[i] * rref;
-          }
-        }
-      }
-    }
-    // carry row r's populations to the next iteration
-#pragma unroll
-    for (int i = 0; i < 9; ++i) gp[i] = g[i];
-    jxp = jx;
-    jyp = jy;
-    stage_barrier();
-
-    if (MODE == MODE_STEP && THERMAL) {
-      EnergyCoef<C> ec_new{};
-      // --------------------------------------------------- stage C(r-2)
-      if (k >= 4) {
-        const int c = r - 2;
-        const bool have = WALLS ? (c >= 0 && c < ny) : true;
-        if (have) {
-          const int yc = WALLS ? c : pmod(c, ny);
-          double tval;
-          const int kind = node_kind(yc, tval);
-          constexpr int km = sl(PH, 3), kc = sl(PH, 2), kq = sl(PH, 1);
-          C Ts;
-          if (kind == T_FREE) {
-            constexpr int kr[3] = {km, kc, kq};
-            C phi[3][3], rr[3][3], uxn[3][3], uyn[3][3];
-#pragma unroll
-            for (int dy = 0; dy < 3; ++dy) {
-              const int sr = kr[dy];
-              phi[dy][0] = s_T[sr][lm];
-              phi[dy][1] = s_T[sr][lane];
-              phi[dy][2] = s_T[sr][lp];
-              rr[dy][0] = C(s_rho[sr][lm]);
-              rr[dy][1] = C(s_rho[sr][lane]);
-              rr[dy][2] = C(s_rho[sr][lp]);
-              uxn[dy][0] = s_ux[sr][lm];
-              uxn[dy][1] = s_ux[sr][lane];
-              uxn[dy][2] = s_ux[sr][lp];
-              uyn[dy][0] = s_uy[sr][lm];
-              uyn[dy][1] = s_uy[sr][lane];
-              uyn[dy][2] = s_uy[sr][lp];
-            }
-            EnergyCoef<C> ec;
-            const C inv_rcv = irho_1 * Q.inv_cv;
-            const C lam0 = Q.lambda_v + Q.dlam * (rr[1][1] - Q.rho_v);
-            ec.ux = uxn[1][1];
-            ec.uy = uyn[1][1];
-            ec.divu = gradx9(uxn) + grady9(uyn);
-            ec.glx = Q.dlam * gradx9(rr);
-            ec.gly = Q.dlam * grady9(rr);
-            ec.lam_rcv = lam0 * inv_rcv;
-            ec.inv_rcv = inv_rcv;
-            const C dpdt_n = dpdt_at(a1_2, a2_2, phi[1][1], Q);
-            Ts = phi[1][1] + C(0.5) * energy_rhs(phi, ec, dpdt_n);
-            ec.dpdt_s = dpdt_at(a1_2, a2_2, Ts, Q);
-            ec_new = ec;
-          } else {
-            Ts = C(tval);  // ADIABATIC rows are substituted by the reader
-          }
-          s_Ts[kc][lane] = Ts;
-        }
-      }
-      stage_barrier();
-      // --------------------------------------------------- stage D(r-3)
-      if (k >= 6) {
-        const int d = r - 3;
-        if (d >= y0 && d < y1) {
-          const int yd = d;
-          double tval;
-          const int kind = node_kind(yd, tval);
-          constexpr int km = sl(PH, 4), kc = sl(PH, 3), kq = sl(PH, 2);
-          char* trow = Tout + size_t(__builtin_amdgcn_readfirstlane(yd)) * row_b;
-          if (kind == T_FREE) {
-            C phi[3][3];
-            phi[0][0] = s_Ts[km][lm];
-            phi[0][1] = s_Ts[km][lane];
-            phi[0][2] = s_Ts[km][lp];
-            phi[1][0] = s_Ts[kc][lm];
-            phi[1][1] = s_Ts[kc][lane];
-            phi[1][2] = s_Ts[kc][lp];
-            phi[2][0] = s_Ts[kq][lm];
-            phi[2][1] = s_Ts[kq][lane];
-            phi[2][2] = s_Ts[kq][lp];
-            // adiabatic rows 0 / ny-1 take the stage value of their neighbour row
-            if (yd == 1) {
-#pragma unroll
-              for (int j = 0; j < 3; ++j) {
-                double tv;
-                if (row_kind(0, j, tv) == T_ADIABATIC) phi[0][j] = phi[1][j];
-              }
-            }
-            if (yd == ny - 2) {
-#pragma unroll
-              for (int j = 0; j < 3; ++j) {
-                double tv;
-                if (row_kind(ny - 1, j, tv) == T_ADIABATIC) phi[2][j] = phi[1][j];
-              }
-            }
-            const C T0 = s_T[kc][lane];
-            const C Tnew = T0 + energy_rhs(phi, ec_prev, ec_prev.dpdt_s);
-            if (outlane) {
-              st(trow, ox, S(Tnew));
-              double tv;
-              if (yd == 1 && row_kind(0, 1, tv) == T_ADIABATIC) st(Tout, ox, S(Tnew));
-              if (yd == ny - 2 && row_kind(ny - 1, 1, tv) == T_ADIABATIC)
-                st(Tout + size_t(ny - 1) * row_b, ox, S(Tnew));
-            }
-          } else if (kind == T_DIRICHLET) {
-            if (outlane) st(trow, ox, S(tval));
-          }
-        }
-      }
-      ec_prev = ec_new;  // row r-2 is stage D's row of the next iteration
-      stage_barrier();
-    }
-    // shift the per-lane carries by one row
-    a1_2 = a1_1;
-    a2_2 = a2_1;
-    a1_1 = a1;
-    a2_1 = a2;
-    irho_1 = irho_new;
   };
 
-  // the row loop, unrolled by 4 so that every ring slot is a constant
-  for (int kb = 0; kb < nit; kb += 4) {
+  // ---------------------------------------------------------- wall closures
+  // wall row in slot SW, its interior neighbour row in slot SN
+  auto closure = [&](auto swc, auto snc, const bool bottom) {
+    constexpr int SW = decltype(swc)::value, SN = decltype(snc)::value;
+    const double sgn = bottom ? 1.0 : -1.0;
+    const double K = s_rho[SW][lane];
+    const double Tw = double(s_T[SW][lane]);
+    const double rw = A.tabd[(bottom ? 0 : 1) * nx + x];
+    const double psiw = psi_checked(rw, Tw, P, err);
+    const double B = wall_coef_B(s_psi[SN][lane], s_psi[SN][lp], s_psi[SN][lm], psiw, sgn, P);
+    const double rwall = wall_density(K, B, Tw, sgn, P);
+    s_rho[SW][lane] = rwall;
+    if constexpr (kRhoC) s_rc[SW][lane] = C(rwall);
+    s_psi[SW][lane] = psi_checked(rwall, Tw, P, err);
+    if (bottom) psiw_b = psiw; else psiw_t = psiw;
+  };
+
+  // ------------------------------------------------------------ stage B(s)
+  // forces, velocity and collision of row s (slot SB); gp are its pulled
+  // populations, (jxs, jys) its momentum
+  auto stageB = [&](auto sbc, const int s, const C (&gin)[9], C jxs, C jys, C& irho_out) {
+    constexpr int SB = decltype(sbc)::value;
+    constexpr int km = (SB + R - 1) & (R - 1), kc = SB, kq = (SB + 1) & (R - 1);  // rows s-1, s, s+1
+    const bool have = WALLS ? (s >= 0 && s < ny) : true;
+    if (!have) return;
+    C gp[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) gp[i] = gin[i];
+    const int ys = WALLS ? s : wrap3(s, ny);
+    const bool wb = WALLS && ys == 0, wt = WALLS && ys == ny - 1;
+    const double pc = s_psi[kc][lane];
+    const double p1 = s_psi[kc][lp], p3 = s_psi[kc][lm];
+    double p2, p5, p6, p4, p7, p8;
+    if (wt) {
+      p2 = p5 = p6 = psiw_t;
+    } else {
+      p2 = s_psi[kq][lane];
+      p5 = s_psi[kq][lp];
+      p6 = s_psi[kq][lm];
+    }
+    if (wb) {
+      p4 = p7 = p8 = psiw_b;
+    } else {
+      p4 = s_psi[km][lane];
+      p7 = s_psi[km][lm];
+      p8 = s_psi[km][lp];
+    }
+    const double rho = s_rho[kc][lane];
+    const double G = P.G;
+    // Eq. shanchen (psi_w for solid neighbours: Eq. shanchen-walls)
+    const double d1 = p1 - pc, d2 = p2 - pc, d3 = p3 - pc, d4 = p4 - pc;
+    const double d5 = p5 - pc, d6 = p6 - pc, d7 = p7 - pc, d8 = p8 - pc;
+    const double sx = (1.0 / 3.0) * (p1 - p3) + (1.0 / 12.0) * ((p5 - p7) + (p8 - p6));
+    const double sy = (1.0 / 3.0) * (p2 - p4) + (1.0 / 12.0) * ((p5 - p7) + (p6 - p8));
+    const double fmx = -G * pc * sx;
+    const double fmy = -G * pc * sy;
+    const double fx = fmx;
+    const double fy = fmy + P.gy * (rho - rho_bar);
+    // Eq. Q / Q-psi-based
+    const double kq2 = P.kappa * G * 0.5 * pc;
+    const double dsum = (d5 + d6) + (d7 + d8);
+    const double qxx = kq2 * ((1.0 / 3.0) * (d1 + d3) + (1.0 / 12.0) * dsum);
+    const double qyy = kq2 * ((1.0 / 3.0) * (d2 + d4) + (1.0 / 12.0) * dsum);
+    const double qxy = kq2 * ((1.0 / 12.0) * ((d5 + d7) - (d6 + d8)));
+
+    if (wb || wt) {
+      // Zou-He reconstruction for the prescribed momentum -F^m/2
+      jxs = C(-0.5 * fmx);
+      jys = C(-0.5 * fmy);
+      const C d = C(0.5) * (gp[1] - gp[3]);
+      if (wb) {
+        gp[2] = gp[4] + C(2.0 / 3.0) * jys;
+        gp[5] = gp[7] - d + C(0.5) * jxs + jys * C(1.0 / 6.0);
+        gp[6] = gp[8] + d - C(0.5) * jxs + jys * C(1.0 / 6.0);
+      } else {
+        gp[4] = gp[2] - C(2.0 / 3.0) * jys;
+        gp[7] = gp[5] + d - C(0.5) * jxs - jys * C(1.0 / 6.0);
+        gp[8] = gp[6] - d + C(0.5) * jxs - jys * C(1.0 / 6.0);
+      }
+    }
+    const double inv_rho = rcp64(rho);
+    irho_out = C(inv_rho);
+    const double uxd = (double(jxs) + 0.5 * fx) * inv_rho;
+    const double uyd = (double(jys) + 0.5 * fy) * inv_rho;
+    s_ux[kc][lane] = C(uxd);
+    s_uy[kc][lane] = C(uyd);
+
+    const bool inseg = s >= y0 && s < y1 && outlane;
+    if (MODE == MODE_STEP && inseg) {
+      // ---- MRT collision in shifted moments n = M g (g = f - w rho_ref)
+      const C ux = C(uxd), uy = C(uyd), Fx = C(fx), Fy = C(fy), rc = C(rho);
+      const C sg = C(rho - rref);
+      const C a4 = (gp[1] + gp[2]) + (gp[3] + gp[4]);
+      const C d4s = (gp[5] + gp[6]) + (gp[7] + gp[8]);
+      const C n1 = C(-4) * gp[0] - a4 + C(2) * d4s;
+      const C n2 = C(4) * gp[0] - C(2) * a4 + d4s;
+      const C n4 = C(2) * (gp[3] - gp[1]) + (gp[5] - gp[7]) + (gp[8] - gp[6]);
+      const C n6 = C(2) * (gp[4] - gp[2]) + (gp[5] - gp[7]) + (gp[6] - gp[8]);
+      const C n7 = (gp[1] + gp[3]) - (gp[2] + gp[4]);
+      const C n8 = (gp[5] + gp[7]) - (gp[6] + gp[8]);
+      const C u2 = ux * ux + uy * uy;
+      const C uF = ux * Fx + uy * Fy;
+      // sigma term 12 sigma |F^m|^2 / (psi^2 (tau - 1/2))
+      const C fm2_ps2 = C((fmx * fmx + fmy * fmy) * rcp64(pc * pc));
+      const C te = C(P.sig_e) * fm2_ps2, tz = C(P.sig_z) * fm2_ps2;
+      C snu = Q.snu_const;
+      if (Q.snu_varies) {
+        const C eta = Q.eta_v + (Q.eta_l - Q.eta_v) * (rc - Q.rho_v) * Q.inv_drho;
+        snu = rcp_c(C(3) * eta + C(0.5));
+      }
+      const C se = Q.s_e, sz = Q.s_z, sq = Q.s_q;
+      const C qs = C(qxx + qyy), qd = C(qxx - qyy);
+      const C r3u2 = C(3) * rc * u2;
+      const C m0 = sg;
+      const C m1 = n1 - se * (n1 + C(2) * sg - r3u2) + (C(1) - se * C(0.5)) * (C(6) * uF + te) +
+                   C(1.5) * se * qs;
+      const C m2 = n2 - sz * (n2 - sg + r3u2) - (C(1) - sz * C(0.5)) * (C(6) * uF + tz) -
+                   C(1.5) * sz * qs;
+      const C m3 = jxs + Fx;
+      const C m4 = n4 - sq * (n4 + rc * ux) - (C(1) - sq * C(0.5)) * Fx;
+      const C m5 = jys + Fy;
+      const C m6 = n6 - sq * (n6 + rc * uy) - (C(1) - sq * C(0.5)) * Fy;
+      const C hnu = C(1) - snu * C(0.5);
+      const C m7 = n7 - snu * (n7 - rc * (ux * ux - uy * uy)) + hnu * C(2) * (ux * Fx - uy * Fy) -
+                   snu * qd;
+      const C m8 = n8 - snu * (n8 - rc * ux * uy) + hnu * (ux * Fy + uy * Fx) - snu * C(qxy);
+      // f* = M^-1 m*
+      const C a0 = m0 * C(1.0 / 9.0);
+      const C ax0 = a0 - m1 * C(1.0 / 36.0) - m2 * C(1.0 / 18.0);
+      const C dg0 = a0 + m1 * C(1.0 / 18.0) + m2 * C(1.0 / 36.0);
+      const C j3 = m3 * C(1.0 / 6.0), j5 = m5 * C(1.0 / 6.0);
+      const C q4 = m4 * C(1.0 / 6.0), q6 = m6 * C(1.0 / 6.0);
+      const C q4h = m4 * C(1.0 / 12.0), q6h = m6 * C(1.0 / 12.0);
+      const C p7c = m7 * C(0.25), p8c = m8 * C(0.25);
+      C o[9];
+      o[0] = a0 + (m2 - m1) * C(1.0 / 9.0);
+      o[1] = ax0 + j3 - q4 + p7c;
+      o[2] = ax0 + j5 - q6 - p7c;
+      o[3] = ax0 - j3 + q4 + p7c;
+      o[4] = ax0 - j5 + q6 - p7c;
+      o[5] = dg0 + j3 + j5 + q4h + q6h + p8c;
+      o[6] = dg0 - j3 + j5 - q4h + q6h - p8c;
+      o[7] = dg0 - j3 - j5 - q4h - q6h + p8c;
+      o[8] = dg0 + j3 - j5 + q4h - q6h - p8c;
+      char* orow = fout + size_t(__builtin_amdgcn_readfirstlane(ys)) * row_b;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) st(orow + i * plane_b, ox, S(o[i]));
+      if (A.want_mass) {
+        // known-part density of the next step (walls: the populations
+        // leaving through a wall are replaced by those the closure will
+        // rebuild from the neighbour row)
+        double m = rref;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) m += double(S(o[i]));
+        if (WALLS) {
+          const double dn = double(S(o[4])) + double(S(o[7])) + double(S(o[8])) + rref / 6.0;
+          const double up = double(S(o[2])) + double(S(o[5])) + double(S(o[6])) + rref / 6.0;
+          if (ys == 0) m -= dn;
+          if (ys == 1) m += dn;
+          if (ys == ny - 2) m += up;
+          if (ys == ny - 1) m -= up;
+        }
+        mass_acc += m;
+      }
+    }
+    if (MODE == MODE_MACRO && inseg) {
+      const long long id = (long long)ys * nx + x;
+      if (O.rho) O.rho[id] = rho;
+      if (O.ux) O.ux[id] = uxd;
+      if (O.uy) O.uy[id] = uyd;
+      if (O.T) O.T[id] = double(s_T[kc][lane]);
+      if (O.f) {
+        const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                             1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+        const long long N = (long long)nx * ny;
+        for (int i = O.f_first; i < O.f_first + O.f_count; ++i)
+          O.f[(long long)(i - O.f_first) * N + id] = double(gp[i]) + w[i] * rref;
+      }
+    }
+  };
+
+  // ------------------------------------------------------------ stage C(c)
+  // RK2 stage temperature T* of row c (slot SC)
+  auto stageC = [&](auto scc, const int c, const C a1, const C a2, const C irho, EnergyCoef<C>& ec_out) {
+    constexpr int SC = decltype(scc)::value;
+    constexpr int km = (SC + R - 1) & (R - 1), kc = SC, kq = (SC + 1) & (R - 1);
+    const bool have = WALLS ? (c >= 0 && c < ny) : true;
+    if (!have) return;
+    const int yc = WALLS ? c : wrap3(c, ny);
+    double tval;
+    const int kind = node_kind(yc, tval);
+    C Ts;
+    if (kind == T_FREE) {
+      constexpr int kr[3] = {km, kc, kq};
+      C phi[3][3], rr[3][3], uxn[3][3], uyn[3][3];
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) {
+        const int sr = kr[dy];
+        phi[dy][0] = s_T[sr][lm];
+        phi[dy][1] = s_T[sr][lane];
+        phi[dy][2] = s_T[sr][lp];
+        if constexpr (kRhoC) {
+          rr[dy][0] = s_rc[sr][lm];
+          rr[dy][1] = s_rc[sr][lane];
+          rr[dy][2] = s_rc[sr][lp];
+        } else {
+          rr[dy][0] = C(s_rho[sr][lm]);
+          rr[dy][1] = C(s_rho[sr][lane]);
+          rr[dy][2] = C(s_rho[sr][lp]);
+        }
+        uxn[dy][0] = s_ux[sr][lm];
+        uxn[dy][1] = s_ux[sr][lane];
+        uxn[dy][2] = s_ux[sr][lp];
+        uyn[dy][0] = s_uy[sr][lm];
+        uyn[dy][1] = s_uy[sr][lane];
+        uyn[dy][2] = s_uy[sr][lp];
+      }
+      EnergyCoef<C> ec;
+      const C inv_rcv = irho * Q.inv_cv;
+      const C lam0 = Q.lambda_v + Q.dlam * (rr[1][1] - Q.rho_v);
+      ec.ux = uxn[1][1];
+      ec.uy = uyn[1][1];
+      ec.divu = gradx9(uxn) + grady9(uyn);
+      ec.glx = Q.dlam * gradx9(rr);
+      ec.gly = Q.dlam * grady9(rr);
+      ec.lam_rcv = lam0 * inv_rcv;
+      ec.inv_rcv = inv_rcv;
+      const C dpdt_n = dpdt_at(a1, a2, phi[1][1], Q);
+      Ts = phi[1][1] + C(0.5) * energy_rhs(phi, ec, dpdt_n);
+      ec.dpdt_s = dpdt_at(a1, a2, Ts, Q);
+      ec_out = ec;
+    } else {
+      Ts = C(tval);  // ADIABATIC rows are substituted by the reader
+    }
+    s_Ts[kc][lane] = Ts;
+  };
+
+  // ------------------------------------------------------------ stage D(d)
+  // new temperature of row d (slot SD), d inside the strip
+  auto stageD = [&](auto sdc, const int d, const EnergyCoef<C>& ec) {
+    constexpr int SD = decltype(sdc)::value;
+    constexpr int km = (SD + R - 1) & (R - 1), kc = SD, kq = (SD + 1) & (R - 1);
+    const int yd = d;
+    double tval;
+    const int kind = node_kind(yd, tval);
+    char* trow = Tout + size_t(__builtin_amdgcn_readfirstlane(yd)) * row_b;
+    if (kind == T_FREE) {
+      C phi[3][3];
+      phi[0][0] = s_Ts[km][lm];
+      phi[0][1] = s_Ts[km][lane];
+      phi[0][2] = s_Ts[km][lp];
+      phi[1][0] = s_Ts[kc][lm];
+      phi[1][1] = s_Ts[kc][lane];
+      phi[1][2] = s_Ts[kc][lp];
+      phi[2][0] = s_Ts[kq][lm];
+      phi[2][1] = s_Ts[kq][lane];
+      phi[2][2] = s_Ts[kq][lp];
+      // adiabatic rows 0 / ny-1 take the stage value of their neighbour row
+      if (yd == 1) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          double tv;
+          if (row_kind(0, j, tv) == T_ADIABATIC) phi[0][j] = phi[1][j];
+        }
+      }
+      if (yd == ny - 2) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          double tv;
+          if (row_kind(ny - 1, j, tv) == T_ADIABATIC) phi[2][j] = phi[1][j];
+        }
+      }
+      const C T0 = s_T[kc][lane];
+      const C Tnew = T0 + energy_rhs(phi, ec, ec.dpdt_s);
+      if (outlane) {
+        st(trow, ox, S(Tnew));
+        double tv;
+        if (yd == 1 && row_kind(0, 1, tv) == T_ADIABATIC) st(Tout, ox, S(Tnew));
+        if (yd == ny - 2 && row_kind(ny - 1, 1, tv) == T_ADIABATIC)
+          st(Tout + size_t(ny - 1) * row_b, ox, S(Tnew));
+      }
+    } else if (kind == T_DIRICHLET) {
+      if (outlane) st(trow, ox, S(tval));
+    }
+  };
+
+  // one iteration: rows r_j = rbase + RPI k + j through stage A, then the
+  // rows one, two and three behind through stages B, C and D
+  auto body = [&](auto phc, const int k) {
+    constexpr int PH = decltype(phc)::value;
+    const int r0 = rbase + RPI * k;
+    C g[RPI][9], Tr[RPI], jxc[RPI], jyc[RPI], a1c[RPI], a2c[RPI], irc[RPI];
+    EnergyCoef<C> ecc[RPI];
+#pragma unroll
+    for (int j = 0; j < RPI; ++j) {
+      Tr[j] = Tn[j];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) g[j][i] = gn[j][i];
+    }
+#pragma unroll
+    for (int j = 0; j < RPI; ++j)
+      if (r0 + RPI + j < rend) load_row(r0 + RPI + j, gn[j], Tn[j]);
+    static_for<RPI>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      constexpr int S0 = (RPI * PH + j) & (R - 1);
+      jxc[j] = jyc[j] = a1c[j] = a2c[j] = irc[j] = C(0);
+      ecc[j] = EnergyCoef<C>{};
+      if (r0 + j < rend) stageA(Ph<S0>{}, r0 + j, g[j], Tr[j], jxc[j], jyc[j], a1c[j], a2c[j]);
+    });
+    stage_barrier();
+    if (WALLS) {
+      static_for<RPI>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        constexpr int S0 = (RPI * PH + j) & (R - 1), S1 = (S0 + R - 1) & (R - 1);
+        const int r = r0 + j;
+        if (r < rend) {
+          if (r == 1 && 0 >= rbase) closure(Ph<S1>{}, Ph<S0>{}, true);
+          if (r == ny - 1 && ny - 2 >= rbase) closure(Ph<S0>{}, Ph<S1>{}, false);
+        }
+      });
+      stage_barrier();
+    }
+    static_for<RPI>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      constexpr int SB = (RPI * PH + j + R - 1) & (R - 1);
+      const int s = r0 + j - 1;
+      if (s >= rbase + 1 && s <= rend - 2) {
+        if constexpr (j == 0)
+          stageB(Ph<SB>{}, s, gprev, jxprev, jyprev, irc[j]);
+        else
+          stageB(Ph<SB>{}, s, g[j > 0 ? j - 1 : 0], jxc[j > 0 ? j - 1 : 0], jyc[j > 0 ? j - 1 : 0], irc[j]);
+      }
+    });
+#pragma unroll
+    for (int i = 0; i < 9; ++i) gprev[i] = g[RPI - 1][i];
+    jxprev = jxc[RPI - 1];
+    jyprev = jyc[RPI - 1];
+    stage_barrier();
+    if (MODE == MODE_STEP && THERMAL) {
+      static_for<RPI>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        constexpr int SC = (RPI * PH + j + R - 2) & (R - 1);
+        const int c = r0 + j - 2;
+        // EOS terms of row c: stage A two rows back; 1/rho: stage B one row back
+        const C a1 = a1h[RPI == 2 ? j : 0], a2 = a2h[RPI == 2 ? j : 0];
+        const C ir = j == 0 ? irprev : irc[j > 0 ? j - 1 : 0];
+        if (c >= rbase + 2 && c <= rend - 3) stageC(Ph<SC>{}, c, a1, a2, ir, ecc[j]);
+      });
+      stage_barrier();
+      static_for<RPI>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        constexpr int SD = (RPI * PH + j + R - 3) & (R - 1);
+        const int d = r0 + j - 3;
+        if (d >= y0 && d < y1) stageD(Ph<SD>{}, d, j == 0 ? ecprev : ecc[j > 0 ? j - 1 : 0]);
+      });
+      stage_barrier();
+    }
+    // shift the rolling carries by RPI rows
+    if constexpr (RPI == 2) {
+      a1h[0] = a1c[0];
+      a1h[1] = a1c[1];
+      a2h[0] = a2c[0];
+      a2h[1] = a2c[1];
+    } else {
+      a1h[0] = a1h[1];
+      a1h[1] = a1c[0];
+      a2h[0] = a2h[1];
+      a2h[1] = a2c[0];
+    }
+    irprev = irc[RPI - 1];
+    ecprev = ecc[RPI - 1];
+  };
+
+  // the row loop, unrolled by 4 iterations so that every ring slot is a constant
+  const int niter = (nit + RPI - 1) / RPI;
+  for (int kb = 0; kb < niter; kb += 4) {
     body(Ph<0>{}, kb);
-    if (kb + 1 < nit) body(Ph<1>{}, kb + 1);
-    if (kb + 2 < nit) body(Ph<2>{}, kb + 2);
-    if (kb + 3 < nit) body(Ph<3>{}, kb + 3);
+    if (kb + 1 < niter) body(Ph<1>{}, kb + 1);
+    if (kb + 2 < niter) body(Ph<2>{}, kb + 2);
+    if (kb + 3 < niter) body(Ph<3>{}, kb + 3);
   }
 
   if (MODE == MODE_STEP && A.want_mass) {
@@ -629,7 +725,7 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
 template <class S, class C, bool WALLS, bool THERMAL, int MODE>
 __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(WavesPerEU<S>::value, 8)))
 void lbm_march_kernel(StepArgs<S, C> A, MacroOut O) {
-  march_body<S, C, WALLS, THERMAL, MODE>(A, O, blockIdx.x);
+  march_body<S, C, WALLS, THERMAL, MODE, 1>(A, O, blockIdx.x);
 }
 
 // Batched launch over several lattices of one kind (same storage, walls and
@@ -645,7 +741,7 @@ void lbm_march_multi_kernel(const StepArgs<S, C>* __restrict__ desc, const int* 
   int g = 0;
   while (g + 1 < ngrid && b >= start[g + 1]) ++g;
   const MacroOut O{};
-  march_body<S, C, WALLS, THERMAL, MODE_STEP>(desc[g], O, b - start[g]);
+  march_body<S, C, WALLS, THERMAL, MODE_STEP, 1>(desc[g], O, b - start[g]);
 }
 
 // ------------------------------------------------------------- launchers
