@@ -59,28 +59,24 @@ def vaporisation_case(n=512, seed=0):
     return n, n, kw, bnd, rho, T
 
 
-def pool_case(nx=4096, ny=4096):
-    import paper_2201_04560_amd as pp
+def pool_case(nx=4096, ny=4096, level=5):
+    """Pool boiling on nx x ny read as mesh `level` of the refinement
+    procedure (Sec. 3) over a base mesh 2^level times coarser (a = 2/49,
+    g = -3e-5 on the base mesh; a, sigma, kappa and g rescaled per mesh):
+    liquid below 1400/2048 of the height at T_sat = 0.86 T_c, heater strip of
+    width nx/8 at 0.95 T_c (wall density 3.44), adiabatic elsewhere, top
+    wall at T_sat, seeded nucleation half-disk."""
     import workloads as wl
+    from paper_2201_04560_amd.ladder import pool_level
 
-    a = 2.0 / 49.0
-    Tc = pp.pr_critical_temperature(a)
-    Tsat = 0.86 * Tc
-    rv, rl, _ = pp.pr_maxwell(a, Tsat)
-    rho, T = wl.pool(nx, ny, ny * 1400.0 / 2048.0, 2.3, rl, rv, Tsat, seed_radius=8.0, seed=0)
-    kw = dict(a=a, sigma=pp.fit_sigma(a, Tsat), kappa=0.0, rho_l=rl, rho_v=rv, walls=1, thermal=1,
-              gy=-3e-5, cv=5.0, lambda_l=1.95, lambda_v=0.114, rho_ref=rv)
-    kw.update({k: v for k, v in wl.POOL_RATES.items()})
-    h0, h1 = nx // 2 - nx // 16, nx // 2 + nx // 16
-    kb = np.full(nx, 2, np.int32)
-    kb[h0:h1] = 1
-    vb = np.full(nx, Tsat)
-    vb[h0:h1] = 0.95 * Tc
-    rwb = np.full(nx, 6.50)
-    rwb[h0:h1] = 3.44
-    bnd = dict(rho_w_bottom=rwb, rho_w_top=0.38, t_bottom_kind=kb, t_bottom_val=vb, t_top_kind=1,
-               t_top_val=Tsat)
-    return nx, ny, kw, bnd, rho, T
+    L = pool_level(level, base_nx=nx >> level, base_ny=ny >> level, steps0=0)
+    lv, p = L["level"], L["params"]
+    rho, T = wl.pool(nx, ny, ny * 1400.0 / 2048.0, 2.3 * 2 ** level, lv["rho_l"], lv["rho_v"],
+                     lv["T"], seed_radius=8.0 * 2 ** level / 8.0, seed=0)
+    kw = {k: getattr(p, k) for k in ("a", "b", "omega", "sigma", "kappa", "rho_l", "rho_v", "walls",
+                                     "thermal", "gy", "cv", "lambda_l", "lambda_v", "rho_ref",
+                                     "s_rho", "s_e", "s_zeta", "s_j", "s_q", "eta_l", "eta_v")}
+    return nx, ny, kw, L["boundary"], rho, T
 
 
 def device_key():
@@ -353,6 +349,92 @@ def adjoint_bench(nsteps=500, ckpt=50, n=256, fd_entries=8, h=1e-4):
     return out
 
 
+def droplet_stats(rho, rho_l, rho_v):
+    """Equivalent radius of the liquid area, liquid density at the centre and
+    vapour density in the far corners."""
+    ny, nx = rho.shape
+    mid = 0.5 * (rho_l + rho_v)
+    R = float(np.sqrt((rho > mid).sum() / np.pi))
+    y, x = np.mgrid[0:ny, 0:nx]
+    r = np.hypot(x - nx / 2 + 0.5, y - ny / 2 + 0.5)
+    return {"R_eq": R, "rho_centre": float(rho[r < 0.5 * R].mean()),
+            "rho_far": float(rho[r > 0.45 * min(nx, ny) + R / 2].mean())}
+
+
+def pool_heat_flux(precision, steps, every, tune):
+    """Pool boiling 1024 wide x 2048 tall (liquid below 1400, heater 128 wide
+    at 0.95 T_c; mesh 3 of the refinement ladder over a 128 x 256 base with
+    g = -3e-5 there): heat flux entering through the bottom wall
+    (Eq. pool-heat-flux) every `every` steps."""
+    import torch
+
+    from paper_2201_04560_amd import Lattice, make_params
+
+    nx, ny, kw, bnd, rho, T = pool_case(1024, 2048, level=3)
+    lat = Lattice(make_params(nx, ny, precision=precision, **kw))
+    lat.set_boundary(**bnd)
+    lat.init_fields(rho, None, None, T)
+    if tune is not None:
+        tune.tune(lat, device=device_key())
+    q = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps // every):
+        lat.step(every)
+        q.append(lat.norms()["q_bottom"])
+    dt = time.perf_counter() - t0
+    r = lat.fields()[0]
+    lat.close()
+    torch.cuda.empty_cache()
+    return np.array(q), r, nx * ny * steps / dt / 1e6, kw
+
+
+def accuracy_bench(vap_res, case, args, tune):
+    """Float32 shifted storage against the float64 step: droplet radius and
+    coexistence densities after the vaporisation run with rho_ref = rho_v
+    (the timed runs) and rho_ref = mean density; heat flux history of the
+    1024 x 2048 pool."""
+    from paper_2201_04560_amd import LBM_FP32_SHIFTED
+
+    nx, ny, kw, bnd, rho0, T0 = case
+    rl, rv = kw["rho_l"], kw["rho_v"]
+    r64 = vap_res["fp64"]["fields"][0]
+    out = {"vaporisation512": {"after_steps": args.warmup + args.steps,
+                               "fp64": droplet_stats(r64, rl, rv)}}
+    for name, res in (("fp32_rho_ref_rho_v", vap_res["fp32"]),):
+        out["vaporisation512"][name] = droplet_stats(res["fields"][0], rl, rv)
+    kw2 = dict(kw, rho_ref=float(rho0.mean()))
+    r2 = run_lattice((nx, ny, kw2, bnd, rho0, T0), LBM_FP32_SHIFTED, args.warmup, args.steps,
+                     tile_y=vap_res["fp32"]["tile_y"])
+    st = droplet_stats(r2["fields"][0], rl, rv)
+    st["rho_ref"] = kw2["rho_ref"]
+    st["rho_max_rel_vs_fp64"] = rel_err(r2["fields"][0], r64)
+    st["T_max_rel_vs_fp64"] = rel_err(r2["fields"][3], vap_res["fp64"]["fields"][3])
+    out["vaporisation512"]["fp32_rho_ref_mean"] = st
+    steps, every = args.pool_steps, max(args.pool_steps // 10, 1)
+    q32, p32, m32, _ = pool_heat_flux(1, steps, every, tune)
+    q64, p64, m64, _ = pool_heat_flux(0, steps, every, tune)
+    out["pool1024x2048"] = {
+        "steps": steps, "q_in_every": every,
+        "q_in_fp32": q32.tolist(), "q_in_fp64": q64.tolist(),
+        "q_in_max_rel_diff": float(np.abs(q32 - q64).max() / np.abs(q64).max()),
+        "rho_max_rel": rel_err(p32, p64),
+        "MLUPS_fp32_with_norms": round(m32, 1), "MLUPS_fp64_with_norms": round(m64, 1)}
+    return out
+
+
+def optional_section(fn, *a, **kw):
+    """A report section beside the metric: a library error (e.g. a state
+    leaving the EOS domain) is recorded in the JSON instead of ending the run."""
+    from paper_2201_04560_amd import LbmError
+
+    try:
+        return fn(*a, **kw)
+    except LbmError as e:
+        log(f"bench: section {fn.__name__} failed: {e}")
+        return {"error": str(e)}
+
+
 def rel_err(a, b):
     return float(np.abs(a - b).max() / np.abs(b).max())
 
@@ -375,6 +457,9 @@ def main():
                     help="steps of the coarsest ladder mesh (mesh k runs steps0 * 4^k)")
     ap.add_argument("--no-ladder", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--pool-steps", type=int, default=5000,
+                    help="steps of the 1024 x 2048 pool in the float32 accuracy check")
     ap.add_argument("--tile-cache", default=None, help="JSON cache of autotuned strip heights")
     ap.add_argument("--no-autotune", action="store_true",
                     help="library default strip heights instead of the autotuner")
@@ -469,6 +554,9 @@ def main():
             "liquid_fraction_fp32": float((r32 > 0.5 * (case[2]["rho_l"] + case[2]["rho_v"])).mean()),
             "liquid_fraction_fp64": float((r64 > 0.5 * (case[2]["rho_l"] + case[2]["rho_v"])).mean()),
         }
+    if "fp32" in res and "fp64" in res and not args.no_accuracy:
+        log("bench: float32 accuracy (rho_ref variants, pool heat flux)")
+        out["fp32_accuracy"] = optional_section(accuracy_bench, res, case, args, tune)
     if not args.no_sizing:
         pc = pool_case()
         sz = {}
@@ -483,15 +571,16 @@ def main():
                         "tile_y": r["tile_y"],
                         "roofline": roofline(name == "fp32", n2, r["kernel_ms_avg"],
                                              measured_traffic(f"pool4096_{name}", r["tile_y"]))}
-        out["hbm_sized_run"] = {"workload": "pool boiling physics 4096x4096 (walls, heater, "
-                                            "gravity, thermal), 1.3 GB f32 / 2.7 GB f64 state",
+        out["hbm_sized_run"] = {"workload": "pool boiling 4096x4096 (walls, heater, gravity, "
+                                            "energy equation; mesh 5 of the refinement procedure "
+                                            "over a 128x128 base), 1.3 GB f32 / 2.7 GB f64 state",
                                 **sz}
     if not args.no_ladder:
         log(f"bench: refinement ladder, steps0 {args.ladder_steps0}")
-        out["ladder"] = ladder_bench(args.ladder_steps0, tile_cache=args.tile_cache)
+        out["ladder"] = optional_section(ladder_bench, args.ladder_steps0, tile_cache=args.tile_cache)
     if not args.no_adjoint:
         log("bench: adjoint 256x256, 500 steps")
-        out["adjoint"] = adjoint_bench()
+        out["adjoint"] = optional_section(adjoint_bench)
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(case)

@@ -183,3 +183,49 @@ def test_fp32_shifted_tracks_fp64():
     ro, _, _, To = s.fields()
     print("fp32 rho rel", _rel(r, ro), "T rel", _rel(T2, To), flush=True)
     assert _rel(r, ro) < 1e-4 and _rel(T2, To) < 1e-5
+
+
+def _pool_mesh3(precision, tile_y):
+    """The 1024 x 2048 pool (liquid below 1400, heater 128 wide at 0.95 T_c)
+    as mesh 3 of the refinement procedure over a 128 x 256 base mesh."""
+    import workloads as wl
+    from paper_2201_04560_amd import Lattice
+    from paper_2201_04560_amd.ladder import pool_level
+
+    L = pool_level(3, precision=precision, tile_y=tile_y, steps0=0)
+    lv = L["level"]
+    rho, T = wl.pool(1024, 2048, 1400.0, 2.3 * 8, lv["rho_l"], lv["rho_v"], lv["T"], seed_radius=8.0,
+                     seed=0)
+    lat = Lattice(L["params"])
+    lat.set_boundary(**L["boundary"])
+    lat.init_fields(rho, None, None, T)
+    return lat
+
+
+def test_pool_1024x2048_full_size_properties():
+    """Full-size pool boiling in the launch configurations the autotuner
+    picks from: float64 results agree across strip heights (only the order
+    of the rho_bar partial sums differs), the mass moves only through the
+    wall closure, and float32 shifted storage tracks float64."""
+    print("case pool 1024x2048 full size", flush=True)
+    outs = []
+    for ty in (16, 64):
+        lat = _pool_mesh3(0, ty)
+        m0 = lat.norms()["mass"]
+        lat.step(300)
+        n = lat.norms()
+        assert n["nonfinite"] == 0
+        outs.append((lat.fields(), n["mass"] / m0 - 1))
+        lat.close()
+    (r1, u1, v1, T1), dm1 = outs[0]
+    (r2, u2, v2, T2), dm2 = outs[1]
+    print(f"mass drift {dm1:.3e} {dm2:.3e}", flush=True)
+    assert np.abs(r1 - r2).max() <= 1e-12 * np.abs(r1).max()
+    assert np.abs(T1 - T2).max() <= 1e-12 * np.abs(T1).max()
+    assert abs(dm1) < 1e-4
+    lat = _pool_mesh3(1, 16)
+    lat.step(300)
+    r3, _, _, T3 = lat.fields()
+    e = _rel(r3, r1)
+    print(f"fp32 vs fp64 rho rel {e:.2e}", flush=True)
+    assert e < 1e-3
