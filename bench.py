@@ -87,7 +87,7 @@ def device_key():
     return f"{pr.gcnArchName.split(':')[0]}/{pr.multi_processor_count}CU"
 
 
-def run_lattice(case, precision, warmup, steps, want_fields=True, tile_y=0, tune=None):
+def run_lattice(case, precision, warmup, steps, want_fields=True, tile_y=0, tune=None, strip_waves=0):
     """Warm up, then time `steps` launches of the step kernel: host wall
     clock around the whole region, and one pair of HIP events recorded on the
     lattice's stream around the same launches (their mean is the kernel's
@@ -98,7 +98,8 @@ def run_lattice(case, precision, warmup, steps, want_fields=True, tile_y=0, tune
     from paper_2201_04560_amd import Lattice, make_params
 
     nx, ny, kw, bnd, rho, T = case
-    lat = Lattice(make_params(nx, ny, precision=precision, tile_y=tile_y, **kw))
+    lat = Lattice(make_params(nx, ny, precision=precision, tile_y=tile_y, strip_waves=strip_waves,
+                              **kw))
     lat.set_boundary(**bnd)
     lat.init_fields(rho, None, None, T)
     if tile_y == 0 and tune is not None:
@@ -113,7 +114,8 @@ def run_lattice(case, precision, warmup, steps, want_fields=True, tile_y=0, tune
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ev = lat.last_step_ms()
-    out = dict(wall_s=t1 - t0, ev_ms=ev, kernel_ms_avg=ev / steps, launches=steps, tile_y=lat.tile_y)
+    out = dict(wall_s=t1 - t0, ev_ms=ev, kernel_ms_avg=ev / steps, launches=steps, tile_y=lat.tile_y,
+               strip_waves=lat.strip_waves)
     if want_fields:
         out["fields"] = lat.fields()
         out["norms"] = lat.norms()
@@ -131,10 +133,11 @@ def roofline(fp32, nodes, kernel_ms, traffic):
             "alg_bytes_per_launch": b, "kernel_ms_avg": round(kernel_ms, 5)}
 
 
-def measured_traffic(key, tile_y):
+def measured_traffic(key, tile_y, waves):
     """HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a
     copy kernel of known size) from the committed counter summary, valid only
-    for the kernel sources and the strip height they were taken on."""
+    for the kernel sources, strip height and waves per strip they were taken
+    on."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -144,7 +147,7 @@ def measured_traffic(key, tile_y):
                 h.update(fh.read())
         if not t.get("kernel_sources") or t.get("kernel_sha256") != h.hexdigest():
             return None
-        return t.get("per_launch_bytes", {}).get(key, {}).get(str(tile_y))
+        return t.get("per_launch_bytes", {}).get(key, {}).get(f"{tile_y}x{waves}")
     except (OSError, ValueError):
         return None
 
@@ -225,7 +228,8 @@ def ladder_bench(steps0, levels=(0, 1, 2, 3), seeds=(0, 1, 2, 3), tile_cache=Non
     tiles = {}
     for (k, sd), lat in zip(specs, lats32):
         if k not in tiles:
-            tiles[k] = cache.tune(lat, device=dev)
+            # the batched launch runs one wave per strip: tune the height for it
+            tiles[k] = cache.tune(lat, device=dev + "/batch", waves=(1,))[0]
         lat.tile_y = tiles[k]
     log(f"bench: ladder tiles {tiles}, steps {sorted(set(steps))}")
     b = Batch(lats32)
@@ -405,7 +409,7 @@ def accuracy_bench(vap_res, case, args, tune):
         out["vaporisation512"][name] = droplet_stats(res["fields"][0], rl, rv)
     kw2 = dict(kw, rho_ref=float(rho0.mean()))
     r2 = run_lattice((nx, ny, kw2, bnd, rho0, T0), LBM_FP32_SHIFTED, args.warmup, args.steps,
-                     tile_y=vap_res["fp32"]["tile_y"])
+                     tile_y=vap_res["fp32"]["tile_y"], strip_waves=vap_res["fp32"]["strip_waves"])
     st = droplet_stats(r2["fields"][0], rl, rv)
     st["rho_ref"] = kw2["rho_ref"]
     st["rho_max_rel_vs_fp64"] = rel_err(r2["fields"][0], r64)
@@ -508,7 +512,7 @@ def main():
         r = res[name]
         log(f"bench: {name} {args.steps * nodes / r['wall_s'] / 1e6:.0f} MLUPS, kernel "
             f"{r['kernel_ms_avg'] * 1e3:.2f} us avg over {r['launches']} launches, "
-            f"tile_y {r['tile_y']}")
+            f"tile_y {r['tile_y']}, waves {r['strip_waves']}")
 
     main_name = "fp32" if "fp32" in res else "fp64"
     m = res[main_name]
@@ -531,9 +535,10 @@ def main():
                                "gravity, seed 0 (+-0.5 interface jitter)",
                    "nx": nx, "ny": ny, "storage": "f32 shifted populations (f - w rho_v) + f32 T; "
                    "f64 EOS/psi/forces and reductions", "steps_total": args.warmup + args.steps,
-                   "tile_y": m["tile_y"]},
+                   "tile_y": m["tile_y"], "strip_waves": m["strip_waves"]},
         "roofline": roofline(main_name == "fp32", nodes, m["kernel_ms_avg"],
-                             measured_traffic(f"vaporisation512_{main_name}", m["tile_y"])),
+                             measured_traffic(f"vaporisation512_{main_name}", m["tile_y"],
+                                              m["strip_waves"])),
     }
     if "fp32" in res and "fp64" in res:
         f32, f64 = res["fp32"], res["fp64"]
@@ -541,10 +546,10 @@ def main():
         r64, _, _, T64 = f64["fields"]
         out["fp64_plain"] = {
             "value": round(args.steps * nodes / f64["wall_s"] / 1e6, 1), "unit": "MLUPS",
-            "tile_y": f64["tile_y"],
+            "tile_y": f64["tile_y"], "strip_waves": f64["strip_waves"],
             "ms_per_step": round(f64["wall_s"] * 1e3 / args.steps, 5),
             "roofline": roofline(False, nodes, f64["kernel_ms_avg"],
-                                 measured_traffic("vaporisation512_fp64", f64["tile_y"])),
+                                 measured_traffic("vaporisation512_fp64", f64["tile_y"], f64["strip_waves"])),
         }
         out["speedup_fp32_vs_fp64"] = round(f64["wall_s"] / f32["wall_s"], 3)
         out["fp32_error_vs_fp64"] = {
@@ -568,9 +573,10 @@ def main():
             n2 = pc[0] * pc[1]
             sz[name] = {"value": round(args.sizing_steps * n2 / r["wall_s"] / 1e6, 1),
                         "unit": "MLUPS",
-                        "tile_y": r["tile_y"],
+                        "tile_y": r["tile_y"], "strip_waves": r["strip_waves"],
                         "roofline": roofline(name == "fp32", n2, r["kernel_ms_avg"],
-                                             measured_traffic(f"pool4096_{name}", r["tile_y"]))}
+                                             measured_traffic(f"pool4096_{name}", r["tile_y"],
+                                                              r["strip_waves"]))}
         out["hbm_sized_run"] = {"workload": "pool boiling 4096x4096 (walls, heater, gravity, "
                                             "energy equation; mesh 5 of the refinement procedure "
                                             "over a 128x128 base), 1.3 GB f32 / 2.7 GB f64 state",

@@ -79,7 +79,9 @@ typedef struct lbm_params {
   double t_side_val;
   double rho_ref;                /* shift of the float32 storage */
   int32_t xcd_remap;             /* 1: keep neighbouring tiles on one XCD */
-  int32_t reserved_i[7];
+  int32_t strip_waves;           /* waves per strip of the energy step: 1, 2, or 0 = by lattice
+                                    size (2 on lattices with fewer than 2048 five-row strips) */
+  int32_t reserved_i[6];
   double reserved_d[8];
 } lbm_params;
 
@@ -154,6 +156,12 @@ lbm_status lbm_load_state(lbm_ctx* ctx, const void* host, size_t bytes);
  * changes with it otherwise). */
 lbm_status lbm_set_tile_y(lbm_ctx* ctx, int32_t tile_y);
 int32_t lbm_get_tile_y(const lbm_ctx* ctx);
+/* Waves marching each strip in the energy step: 1 (one wave, all stages),
+ * 2 (a second wave takes the RK2 stages one row behind), 0 = by lattice
+ * size.  Identical results; a performance choice.  get returns the
+ * effective value. */
+lbm_status lbm_set_strip_waves(lbm_ctx* ctx, int32_t waves);
+int32_t lbm_get_strip_waves(const lbm_ctx* ctx);
 
 /* Wait for the context stream; report sticky device errors. */
 lbm_status lbm_sync(lbm_ctx* ctx);

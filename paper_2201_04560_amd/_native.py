@@ -25,7 +25,7 @@ class LbmParams(ctypes.Structure):
         ("eta_l", c_double), ("eta_v", c_double), ("rho_l", c_double), ("rho_v", c_double),
         ("gy", c_double), ("cv", c_double), ("lambda_l", c_double), ("lambda_v", c_double),
         ("t_side_val", c_double), ("rho_ref", c_double),
-        ("xcd_remap", c_int32), ("reserved_i", c_int32 * 7), ("reserved_d", c_double * 8),
+        ("xcd_remap", c_int32), ("strip_waves", c_int32), ("reserved_i", c_int32 * 6), ("reserved_d", c_double * 8),
     ]
 
 
@@ -69,6 +69,8 @@ SIGNATURES = [
     ("lbm_kernel_timing", c_int32, [c_void_p, c_int32]),
     ("lbm_set_tile_y", c_int32, [c_void_p, c_int32]),
     ("lbm_get_tile_y", c_int32, [c_void_p]),
+    ("lbm_set_strip_waves", c_int32, [c_void_p, c_int32]),
+    ("lbm_get_strip_waves", c_int32, [c_void_p]),
     ("lbm_batch_bytes", c_int32, [c_int32, P(c_size_t)]),
     ("lbm_batch_create", c_int32, [P(c_void_p), c_int32, c_void_p, c_size_t, c_void_p, P(c_void_p)]),
     ("lbm_batch_destroy", None, [c_void_p]),

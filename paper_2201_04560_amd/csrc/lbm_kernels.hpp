@@ -27,6 +27,7 @@ struct LaunchStep {
   long long plane;
   int ty, ntx, nty, halo;
   int walls, update_T, side_dir, want_mass, xcd_remap;
+  int waves;  // 2: energy step marched by two waves per strip
   Phys ph;
   double* o_rho;
   double* o_ux;

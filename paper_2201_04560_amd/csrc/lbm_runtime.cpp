@@ -23,16 +23,23 @@ constexpr int kNormBlocks = 512;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Small lattices (fewer than 2048 five-row strips) are bound by one wave's
+// per-row latency: their energy step runs two waves per strip (the second
+// wave takes the RK2 stages) on 5-row strips.
+bool small_lattice(int nx, int ny, int walls) {
+  const int ntx = (nx + tile_x(walls) - 1) / tile_x(walls);
+  return static_cast<long long>(ntx) * ((ny + 4) / 5) < 2048;
+}
+
 int default_tile_y(int nx, int ny, int walls, int fp32) {
   // The longest strip that still gives every SIMD about two one-wave
   // workgroups (float64: one and a half): long strips recompute fewer of
-  // the 6 halo rows, but a lattice too small for that runs at the shortest
-  // strips, where the step is bound by one wave's per-row latency (measured
-  // on MI355X: 512^2 -> 3 rows (float32) / 5 rows (float64), 4096^2 -> 64).
+  // the 6 halo rows (measured on MI355X: 4096^2 -> 64-128 rows).
+  if (small_lattice(nx, ny, walls)) return std::max(2, std::min(5, std::max(ny, 2)));
   const int ntx = (nx + tile_x(walls) - 1) / tile_x(walls);
   const int want = fp32 ? 2048 : 1536;
-  static const int cand[] = {64, 48, 32, 24, 16, 12, 8, 6, 5, 4, 3};
-  int ty = fp32 ? 3 : 5;
+  static const int cand[] = {64, 48, 32, 24, 16, 12, 8, 6, 5};
+  int ty = 5;
   for (int c : cand) {
     if (static_cast<long long>(ntx) * ((ny + c - 1) / c) >= want) {
       ty = c;
@@ -40,6 +47,11 @@ int default_tile_y(int nx, int ny, int walls, int fp32) {
     }
   }
   return std::max(2, std::min(ty, std::max(ny, 2)));
+}
+
+int strip_waves(const lbm_ctx* c) {
+  if (c->p.strip_waves == 1 || c->p.strip_waves == 2) return c->p.strip_waves;
+  return small_lattice(c->p.nx, c->p.ny, c->p.walls) ? 2 : 1;
 }
 
 }  // namespace
@@ -180,6 +192,7 @@ lbm_status lbm_validate(const lbm_params* p) {
   }
   if (p->n_iso < 0) return bad("n_iso must be >= 0");
   if (p->tile_y < 0 || p->tile_y == 1) return bad("tile_y must be 0 or >= 2");
+  if (p->strip_waves < 0 || p->strip_waves > 2) return bad("strip_waves must be 0, 1 or 2");
   if (!std::isfinite(p->rho_ref)) return bad("rho_ref must be finite");
   return LBM_OK;
 }
@@ -382,6 +395,7 @@ LaunchStep lbm::step_args(lbm_ctx* c) {
   L.walls = c->p.walls;
   L.side_dir = c->p.t_side_dirichlet;
   L.xcd_remap = c->p.xcd_remap;
+  L.waves = strip_waves(c);
   L.ph = c->ph;
   return L;
 }
@@ -416,6 +430,15 @@ lbm_status lbm_set_tile_y(lbm_ctx* c, int32_t tile_y) {
 }
 
 int32_t lbm_get_tile_y(const lbm_ctx* c) { return c ? c->L.ty : -1; }
+
+lbm_status lbm_set_strip_waves(lbm_ctx* c, int32_t waves) {
+  if (!c) return LBM_E_INVAL;
+  if (waves < 0 || waves > 2) return fail(c, LBM_E_INVAL, "strip_waves must be 0, 1 or 2");
+  c->p.strip_waves = waves;
+  return LBM_OK;
+}
+
+int32_t lbm_get_strip_waves(const lbm_ctx* c) { return c ? strip_waves(c) : -1; }
 
 lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
   if (!c) return LBM_E_INVAL;

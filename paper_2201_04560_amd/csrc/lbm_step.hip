@@ -143,9 +143,16 @@ using Ph = std::integral_constant<int, N>;
 // RPI; 1 is instantiated: with 2 (two independent row chains per wave) the
 // step ran 3-6 % slower on 512^2 and up to 60 % slower on 4096^2 on MI355X
 // (more registers, no gain in overlap).
-template <class S, class C, bool WALLS, bool THERMAL, int MODE, int RPI>
+// WS (energy step only): the strip is marched by two waves of one
+// workgroup, wave 0 through stages A and B, wave 1 through C and D one row
+// later; they exchange rows through LDS rings of 8 rows and meet at one
+// workgroup barrier per row.  Handing the collision to wave 1 as well (21
+// values per node through LDS) measured slower on MI355X.
+template <class S, class C, bool WALLS, bool THERMAL, int MODE, int RPI, bool WS>
 __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroOut& O, const int bid) {
-  const int lane = threadIdx.x;
+  static_assert(!WS || (MODE == MODE_STEP && THERMAL && RPI == 1), "two-wave march: energy step only");
+  const int lane = WS ? int(threadIdx.x & (kLanes - 1)) : int(threadIdx.x);
+  const int wave = WS ? __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)) : 0;
   const int nb = A.ntx * A.nty;
   if (bid >= nb) return;  // padding workgroup of a batched launch
   const int tile = tile_of_block(bid, nb, A.xcd_remap);
@@ -179,7 +186,7 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
   auto st = [](char* base, uint32_t off, S v) { *reinterpret_cast<S*>(base + off) = v; };
 
   // rings of R rows indexed by (row - first row) & (R - 1)
-  constexpr int R = 4 * RPI;  // ring rows
+  constexpr int R = WS ? 8 : 4 * RPI;  // ring rows
   __shared__ double s_rho[R][kLanes];
   __shared__ double s_psi[R][kLanes];
   __shared__ C s_T[R][kLanes];
@@ -190,6 +197,11 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
   // the float64 path reads s_rho)
   constexpr bool kRhoC = sizeof(C) < sizeof(double);
   __shared__ C s_rc[kRhoC ? R : 1][kLanes];
+  // two-wave march: EOS terms and 1/rho handed from wave 0 to wave 1
+  __shared__ C s_a1[WS ? R : 1][kLanes];
+  __shared__ C s_a2[WS ? R : 1][kLanes];
+  __shared__ C s_ir[WS ? R : 1][kLanes];
+  constexpr int kColl = 21;  // collision inputs of a node
 
   // mean density of the current state (Eq. gravitational_force): the
   // partials are summed in the same order by every workgroup
@@ -291,7 +303,7 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
   // moments, EOS and psi of row r (slot SA); wall rows keep the known part
   // of their density until the closure
   auto stageA = [&](auto sa, const int r, C (&g)[9], const C Tr, C& jx, C& jy, C& a1, C& a2) {
-    constexpr int SA = decltype(sa)::value;
+    const int SA = int(sa);
     jx = C(0);
     jy = C(0);
     a1 = C(0);
@@ -330,7 +342,7 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
   // ---------------------------------------------------------- wall closures
   // wall row in slot SW, its interior neighbour row in slot SN
   auto closure = [&](auto swc, auto snc, const bool bottom) {
-    constexpr int SW = decltype(swc)::value, SN = decltype(snc)::value;
+    const int SW = int(swc), SN = int(snc);
     const double sgn = bottom ? 1.0 : -1.0;
     const double K = s_rho[SW][lane];
     const double Tw = double(s_T[SW][lane]);
@@ -344,12 +356,90 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
     if (bottom) psiw_b = psiw; else psiw_t = psiw;
   };
 
+  // MRT collision of one row from its inputs ci (pulled populations, jx, jy,
+  // ux, uy, Fx, Fy, rho, rho - rho_ref, |F^m|^2/psi^2, Qxx + Qyy, Qxx - Qyy,
+  // Qxy) in shifted moments n = M g (g = f - w rho_ref); stores the row
+  auto collide_store = [&](const int ys, const C (&ci)[kColl]) {
+    const C* gp = ci;
+    const C jxs = ci[9], jys = ci[10], ux = ci[11], uy = ci[12], Fx = ci[13], Fy = ci[14];
+    const C rc = ci[15], sg = ci[16], fm2_ps2 = ci[17], qs = ci[18], qd = ci[19], qxyc = ci[20];
+    const C a4 = (gp[1] + gp[2]) + (gp[3] + gp[4]);
+    const C d4s = (gp[5] + gp[6]) + (gp[7] + gp[8]);
+    const C n1 = C(-4) * gp[0] - a4 + C(2) * d4s;
+    const C n2 = C(4) * gp[0] - C(2) * a4 + d4s;
+    const C n4 = C(2) * (gp[3] - gp[1]) + (gp[5] - gp[7]) + (gp[8] - gp[6]);
+    const C n6 = C(2) * (gp[4] - gp[2]) + (gp[5] - gp[7]) + (gp[6] - gp[8]);
+    const C n7 = (gp[1] + gp[3]) - (gp[2] + gp[4]);
+    const C n8 = (gp[5] + gp[7]) - (gp[6] + gp[8]);
+    const C u2 = ux * ux + uy * uy;
+    const C uF = ux * Fx + uy * Fy;
+    const C te = C(P.sig_e) * fm2_ps2, tz = C(P.sig_z) * fm2_ps2;
+    C snu = Q.snu_const;
+    if (Q.snu_varies) {
+      const C eta = Q.eta_v + (Q.eta_l - Q.eta_v) * (rc - Q.rho_v) * Q.inv_drho;
+      snu = rcp_c(C(3) * eta + C(0.5));
+    }
+    const C se = Q.s_e, sz = Q.s_z, sq = Q.s_q;
+    const C r3u2 = C(3) * rc * u2;
+    const C m0 = sg;
+    const C m1 = n1 - se * (n1 + C(2) * sg - r3u2) + (C(1) - se * C(0.5)) * (C(6) * uF + te) +
+                 C(1.5) * se * qs;
+    const C m2 = n2 - sz * (n2 - sg + r3u2) - (C(1) - sz * C(0.5)) * (C(6) * uF + tz) -
+                 C(1.5) * sz * qs;
+    const C m3 = jxs + Fx;
+    const C m4 = n4 - sq * (n4 + rc * ux) - (C(1) - sq * C(0.5)) * Fx;
+    const C m5 = jys + Fy;
+    const C m6 = n6 - sq * (n6 + rc * uy) - (C(1) - sq * C(0.5)) * Fy;
+    const C hnu = C(1) - snu * C(0.5);
+    const C m7 = n7 - snu * (n7 - rc * (ux * ux - uy * uy)) + hnu * C(2) * (ux * Fx - uy * Fy) -
+                 snu * qd;
+    const C m8 = n8 - snu * (n8 - rc * ux * uy) + hnu * (ux * Fy + uy * Fx) - snu * qxyc;
+    // f* = M^-1 m*
+    const C a0 = m0 * C(1.0 / 9.0);
+    const C ax0 = a0 - m1 * C(1.0 / 36.0) - m2 * C(1.0 / 18.0);
+    const C dg0 = a0 + m1 * C(1.0 / 18.0) + m2 * C(1.0 / 36.0);
+    const C j3 = m3 * C(1.0 / 6.0), j5 = m5 * C(1.0 / 6.0);
+    const C q4 = m4 * C(1.0 / 6.0), q6 = m6 * C(1.0 / 6.0);
+    const C q4h = m4 * C(1.0 / 12.0), q6h = m6 * C(1.0 / 12.0);
+    const C p7c = m7 * C(0.25), p8c = m8 * C(0.25);
+    C o[9];
+    o[0] = a0 + (m2 - m1) * C(1.0 / 9.0);
+    o[1] = ax0 + j3 - q4 + p7c;
+    o[2] = ax0 + j5 - q6 - p7c;
+    o[3] = ax0 - j3 + q4 + p7c;
+    o[4] = ax0 - j5 + q6 - p7c;
+    o[5] = dg0 + j3 + j5 + q4h + q6h + p8c;
+    o[6] = dg0 - j3 + j5 - q4h + q6h - p8c;
+    o[7] = dg0 - j3 - j5 - q4h - q6h + p8c;
+    o[8] = dg0 + j3 - j5 + q4h - q6h - p8c;
+    char* orow = fout + size_t(__builtin_amdgcn_readfirstlane(ys)) * row_b;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) st(orow + i * plane_b, ox, S(o[i]));
+    if (A.want_mass) {
+      // known-part density of the next step (walls: the populations
+      // leaving through a wall are replaced by those the closure will
+      // rebuild from the neighbour row)
+      double m = rref;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) m += double(S(o[i]));
+      if (WALLS) {
+        const double dn = double(S(o[4])) + double(S(o[7])) + double(S(o[8])) + rref / 6.0;
+        const double up = double(S(o[2])) + double(S(o[5])) + double(S(o[6])) + rref / 6.0;
+        if (ys == 0) m -= dn;
+        if (ys == 1) m += dn;
+        if (ys == ny - 2) m += up;
+        if (ys == ny - 1) m -= up;
+      }
+      mass_acc += m;
+    }
+  };
+
   // ------------------------------------------------------------ stage B(s)
   // forces, velocity and collision of row s (slot SB); gp are its pulled
   // populations, (jxs, jys) its momentum
   auto stageB = [&](auto sbc, const int s, const C (&gin)[9], C jxs, C jys, C& irho_out) {
-    constexpr int SB = decltype(sbc)::value;
-    constexpr int km = (SB + R - 1) & (R - 1), kc = SB, kq = (SB + 1) & (R - 1);  // rows s-1, s, s+1
+    const int SB = int(sbc);
+    const int km = (SB + R - 1) & (R - 1), kc = SB, kq = (SB + 1) & (R - 1);  // rows s-1, s, s+1
     const bool have = WALLS ? (s >= 0 && s < ny) : true;
     if (!have) return;
     C gp[9];
@@ -416,81 +506,24 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
 
     const bool inseg = s >= y0 && s < y1 && outlane;
     if (MODE == MODE_STEP && inseg) {
-      // ---- MRT collision in shifted moments n = M g (g = f - w rho_ref)
-      const C ux = C(uxd), uy = C(uyd), Fx = C(fx), Fy = C(fy), rc = C(rho);
-      const C sg = C(rho - rref);
-      const C a4 = (gp[1] + gp[2]) + (gp[3] + gp[4]);
-      const C d4s = (gp[5] + gp[6]) + (gp[7] + gp[8]);
-      const C n1 = C(-4) * gp[0] - a4 + C(2) * d4s;
-      const C n2 = C(4) * gp[0] - C(2) * a4 + d4s;
-      const C n4 = C(2) * (gp[3] - gp[1]) + (gp[5] - gp[7]) + (gp[8] - gp[6]);
-      const C n6 = C(2) * (gp[4] - gp[2]) + (gp[5] - gp[7]) + (gp[6] - gp[8]);
-      const C n7 = (gp[1] + gp[3]) - (gp[2] + gp[4]);
-      const C n8 = (gp[5] + gp[7]) - (gp[6] + gp[8]);
-      const C u2 = ux * ux + uy * uy;
-      const C uF = ux * Fx + uy * Fy;
-      // sigma term 12 sigma |F^m|^2 / (psi^2 (tau - 1/2))
-      const C fm2_ps2 = C((fmx * fmx + fmy * fmy) * rcp64(pc * pc));
-      const C te = C(P.sig_e) * fm2_ps2, tz = C(P.sig_z) * fm2_ps2;
-      C snu = Q.snu_const;
-      if (Q.snu_varies) {
-        const C eta = Q.eta_v + (Q.eta_l - Q.eta_v) * (rc - Q.rho_v) * Q.inv_drho;
-        snu = rcp_c(C(3) * eta + C(0.5));
-      }
-      const C se = Q.s_e, sz = Q.s_z, sq = Q.s_q;
-      const C qs = C(qxx + qyy), qd = C(qxx - qyy);
-      const C r3u2 = C(3) * rc * u2;
-      const C m0 = sg;
-      const C m1 = n1 - se * (n1 + C(2) * sg - r3u2) + (C(1) - se * C(0.5)) * (C(6) * uF + te) +
-                   C(1.5) * se * qs;
-      const C m2 = n2 - sz * (n2 - sg + r3u2) - (C(1) - sz * C(0.5)) * (C(6) * uF + tz) -
-                   C(1.5) * sz * qs;
-      const C m3 = jxs + Fx;
-      const C m4 = n4 - sq * (n4 + rc * ux) - (C(1) - sq * C(0.5)) * Fx;
-      const C m5 = jys + Fy;
-      const C m6 = n6 - sq * (n6 + rc * uy) - (C(1) - sq * C(0.5)) * Fy;
-      const C hnu = C(1) - snu * C(0.5);
-      const C m7 = n7 - snu * (n7 - rc * (ux * ux - uy * uy)) + hnu * C(2) * (ux * Fx - uy * Fy) -
-                   snu * qd;
-      const C m8 = n8 - snu * (n8 - rc * ux * uy) + hnu * (ux * Fy + uy * Fx) - snu * C(qxy);
-      // f* = M^-1 m*
-      const C a0 = m0 * C(1.0 / 9.0);
-      const C ax0 = a0 - m1 * C(1.0 / 36.0) - m2 * C(1.0 / 18.0);
-      const C dg0 = a0 + m1 * C(1.0 / 18.0) + m2 * C(1.0 / 36.0);
-      const C j3 = m3 * C(1.0 / 6.0), j5 = m5 * C(1.0 / 6.0);
-      const C q4 = m4 * C(1.0 / 6.0), q6 = m6 * C(1.0 / 6.0);
-      const C q4h = m4 * C(1.0 / 12.0), q6h = m6 * C(1.0 / 12.0);
-      const C p7c = m7 * C(0.25), p8c = m8 * C(0.25);
-      C o[9];
-      o[0] = a0 + (m2 - m1) * C(1.0 / 9.0);
-      o[1] = ax0 + j3 - q4 + p7c;
-      o[2] = ax0 + j5 - q6 - p7c;
-      o[3] = ax0 - j3 + q4 + p7c;
-      o[4] = ax0 - j5 + q6 - p7c;
-      o[5] = dg0 + j3 + j5 + q4h + q6h + p8c;
-      o[6] = dg0 - j3 + j5 - q4h + q6h - p8c;
-      o[7] = dg0 - j3 - j5 - q4h - q6h + p8c;
-      o[8] = dg0 + j3 - j5 + q4h - q6h - p8c;
-      char* orow = fout + size_t(__builtin_amdgcn_readfirstlane(ys)) * row_b;
+      // collision inputs in the compute type
+      C ci[kColl];
 #pragma unroll
-      for (int i = 0; i < 9; ++i) st(orow + i * plane_b, ox, S(o[i]));
-      if (A.want_mass) {
-        // known-part density of the next step (walls: the populations
-        // leaving through a wall are replaced by those the closure will
-        // rebuild from the neighbour row)
-        double m = rref;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) m += double(S(o[i]));
-        if (WALLS) {
-          const double dn = double(S(o[4])) + double(S(o[7])) + double(S(o[8])) + rref / 6.0;
-          const double up = double(S(o[2])) + double(S(o[5])) + double(S(o[6])) + rref / 6.0;
-          if (ys == 0) m -= dn;
-          if (ys == 1) m += dn;
-          if (ys == ny - 2) m += up;
-          if (ys == ny - 1) m -= up;
-        }
-        mass_acc += m;
-      }
+      for (int i = 0; i < 9; ++i) ci[i] = gp[i];
+      ci[9] = jxs;
+      ci[10] = jys;
+      ci[11] = C(uxd);
+      ci[12] = C(uyd);
+      ci[13] = C(fx);
+      ci[14] = C(fy);
+      ci[15] = C(rho);
+      ci[16] = C(rho - rref);
+      // sigma term 12 sigma |F^m|^2 / (psi^2 (tau - 1/2)) without the constant
+      ci[17] = C((fmx * fmx + fmy * fmy) * rcp64(pc * pc));
+      ci[18] = C(qxx + qyy);
+      ci[19] = C(qxx - qyy);
+      ci[20] = C(qxy);
+      collide_store(ys, ci);
     }
     if (MODE == MODE_MACRO && inseg) {
       const long long id = (long long)ys * nx + x;
@@ -511,8 +544,8 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
   // ------------------------------------------------------------ stage C(c)
   // RK2 stage temperature T* of row c (slot SC)
   auto stageC = [&](auto scc, const int c, const C a1, const C a2, const C irho, EnergyCoef<C>& ec_out) {
-    constexpr int SC = decltype(scc)::value;
-    constexpr int km = (SC + R - 1) & (R - 1), kc = SC, kq = (SC + 1) & (R - 1);
+    const int SC = int(scc);
+    const int km = (SC + R - 1) & (R - 1), kc = SC, kq = (SC + 1) & (R - 1);
     const bool have = WALLS ? (c >= 0 && c < ny) : true;
     if (!have) return;
     const int yc = WALLS ? c : wrap3(c, ny);
@@ -520,7 +553,7 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
     const int kind = node_kind(yc, tval);
     C Ts;
     if (kind == T_FREE) {
-      constexpr int kr[3] = {km, kc, kq};
+      const int kr[3] = {km, kc, kq};
       C phi[3][3], rr[3][3], uxn[3][3], uyn[3][3];
 #pragma unroll
       for (int dy = 0; dy < 3; ++dy) {
@@ -567,8 +600,8 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
   // ------------------------------------------------------------ stage D(d)
   // new temperature of row d (slot SD), d inside the strip
   auto stageD = [&](auto sdc, const int d, const EnergyCoef<C>& ec) {
-    constexpr int SD = decltype(sdc)::value;
-    constexpr int km = (SD + R - 1) & (R - 1), kc = SD, kq = (SD + 1) & (R - 1);
+    const int SD = int(sdc);
+    const int km = (SD + R - 1) & (R - 1), kc = SD, kq = (SD + 1) & (R - 1);
     const int yd = d;
     double tval;
     const int kind = node_kind(yd, tval);
@@ -700,18 +733,75 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
     ecprev = ecc[RPI - 1];
   };
 
-  // the row loop, unrolled by 4 iterations so that every ring slot is a constant
-  const int niter = (nit + RPI - 1) / RPI;
-  for (int kb = 0; kb < niter; kb += 4) {
-    body(Ph<0>{}, kb);
-    if (kb + 1 < niter) body(Ph<1>{}, kb + 1);
-    if (kb + 2 < niter) body(Ph<2>{}, kb + 2);
-    if (kb + 3 < niter) body(Ph<3>{}, kb + 3);
+  if constexpr (!WS) {
+    // the row loop, unrolled by 4 iterations so that every ring slot is a constant
+    const int niter = (nit + RPI - 1) / RPI;
+    for (int kb = 0; kb < niter; kb += 4) {
+      body(Ph<0>{}, kb);
+      if (kb + 1 < niter) body(Ph<1>{}, kb + 1);
+      if (kb + 2 < niter) body(Ph<2>{}, kb + 2);
+      if (kb + 3 < niter) body(Ph<3>{}, kb + 3);
+    }
+  } else {
+    // two waves, one barrier per iteration; iteration k: wave 0 takes row
+    // r = rbase + k through A and r - 1 through B; wave 1 takes r - 3 through
+    // C and r - 4 through D, all of whose inputs wave 0 wrote in earlier
+    // iterations.  Ring slot of row q: (q - rbase) & 7; in iteration k wave
+    // 0 writes rows r, r - 1 while wave 1 reads rows >= r - 5.
+    const int niter = nit + 1;
+    if (wave == 0) {
+      for (int k = 0; k < niter; ++k) {
+        const int r = rbase + k;
+        const int sr = k & (R - 1), sr1 = (k + R - 1) & (R - 1);
+        if (k < nit) {
+          C g[9], jx, jy, a1, a2;
+#pragma unroll
+          for (int i = 0; i < 9; ++i) g[i] = gn[0][i];
+          const C Tr = Tn[0];
+          if (r + 1 < rend) load_row(r + 1, gn[0], Tn[0]);
+          stageA(sr, r, g, Tr, jx, jy, a1, a2);
+          s_a1[sr][lane] = a1;
+          s_a2[sr][lane] = a2;
+          stage_barrier();
+          if (WALLS) {
+            if (r == 1 && 0 >= rbase) closure(sr1, sr, true);
+            if (r == ny - 1 && ny - 2 >= rbase) closure(sr, sr1, false);
+            stage_barrier();
+          }
+          const int sB = r - 1;
+          if (sB >= rbase + 1 && sB <= rend - 2) {
+            C ir = C(0);
+            stageB(sr1, sB, gprev, jxprev, jyprev, ir);
+            s_ir[sr1][lane] = ir;
+          }
+#pragma unroll
+          for (int i = 0; i < 9; ++i) gprev[i] = g[i];
+          jxprev = jx;
+          jyprev = jy;
+        }
+        __syncthreads();
+      }
+    } else {
+      EnergyCoef<C> ecw{};
+      for (int k = 0; k < niter; ++k) {
+        const int r = rbase + k;
+        const int c = r - 3, d = r - 4;
+        EnergyCoef<C> ecn{};
+        if (c >= rbase + 2 && c <= rend - 3) {
+          const int sc = (k + R - 3) & (R - 1);
+          stageC(sc, c, s_a1[sc][lane], s_a2[sc][lane], s_ir[sc][lane], ecn);
+        }
+        stage_barrier();
+        if (d >= y0 && d < y1) stageD((k + R - 4) & (R - 1), d, ecw);
+        ecw = ecn;
+        __syncthreads();
+      }
+    }
   }
 
   if (MODE == MODE_STEP && A.want_mass) {
     const double tot = wave_sum(mass_acc);
-    if (lane == 0) A.part_out[bid] = tot;
+    if (lane == 0 && wave == 0) A.part_out[bid] = tot;
   }
   const unsigned long long any = __ballot(err != 0);
   if (any) {
@@ -725,7 +815,15 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
 template <class S, class C, bool WALLS, bool THERMAL, int MODE>
 __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(WavesPerEU<S>::value, 8)))
 void lbm_march_kernel(StepArgs<S, C> A, MacroOut O) {
-  march_body<S, C, WALLS, THERMAL, MODE, 1>(A, O, blockIdx.x);
+  march_body<S, C, WALLS, THERMAL, MODE, 1, false>(A, O, blockIdx.x);
+}
+
+// the energy step with two waves per strip (see march_body)
+template <class S, class C, bool WALLS>
+__global__ __launch_bounds__(2 * kLanes) __attribute__((amdgpu_waves_per_eu(WavesPerEU<S>::value, 8)))
+void lbm_march2_kernel(StepArgs<S, C> A) {
+  const MacroOut O{};
+  march_body<S, C, WALLS, true, MODE_STEP, 1, true>(A, O, blockIdx.x);
 }
 
 // Batched launch over several lattices of one kind (same storage, walls and
@@ -741,7 +839,7 @@ void lbm_march_multi_kernel(const StepArgs<S, C>* __restrict__ desc, const int* 
   int g = 0;
   while (g + 1 < ngrid && b >= start[g + 1]) ++g;
   const MacroOut O{};
-  march_body<S, C, WALLS, THERMAL, MODE_STEP, 1>(desc[g], O, b - start[g]);
+  march_body<S, C, WALLS, THERMAL, MODE_STEP, 1, false>(desc[g], O, b - start[g]);
 }
 
 // ------------------------------------------------------------- launchers
@@ -811,6 +909,11 @@ static hipError_t launch_step_t(const LaunchStep& L, hipStream_t st, int mode) {
   if (mode == MODE_MACRO) {
     if (L.walls) launch_one<S, C, true, false, MODE_MACRO>(a, o, nb, st);
     else launch_one<S, C, false, false, MODE_MACRO>(a, o, nb, st);
+  } else if (L.update_T && L.waves == 2) {
+    if (L.walls)
+      hipLaunchKernelGGL((lbm_march2_kernel<S, C, true>), dim3(nb), dim3(2 * kLanes), 0, st, a);
+    else
+      hipLaunchKernelGGL((lbm_march2_kernel<S, C, false>), dim3(nb), dim3(2 * kLanes), 0, st, a);
   } else if (L.walls) {
     if (L.update_T) launch_one<S, C, true, true, MODE_STEP>(a, o, nb, st);
     else launch_one<S, C, true, false, MODE_STEP>(a, o, nb, st);

@@ -73,22 +73,30 @@ class TileCache:
                 f"thermal{p.thermal}/{device}")
 
     def lookup(self, p, device=""):
+        """(tile_y, strip_waves) or None."""
         e = self.table.get(self.key(p, device))
-        return None if e is None else int(e["tile_y"])
+        return None if e is None else (int(e["tile_y"]), int(e.get("strip_waves", 1)))
 
     def tune(self, lattice, candidates=(2, 3, 4, 5, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128), steps=20,
-             device=""):
-        """Cached strip height for this lattice, autotuning (and storing) it on
-        a miss; the lattice's tile_y is set either way.  Returns tile_y."""
-        ty = self.lookup(lattice.p, device)
-        if ty is None:
-            ty, ms = lattice.autotune_tile_y(candidates, steps)
-            self.table[self.key(lattice.p, device)] = {"tile_y": ty, "ms_per_step": ms,
+             device="", waves=(1, 2)):
+        """Cached strip height and waves per strip for this lattice,
+        autotuning (and storing) them on a miss; the lattice is set to them
+        either way.  Returns (tile_y, strip_waves)."""
+        hit = self.lookup(lattice.p, device)
+        if hit is None:
+            best = None
+            for w in (waves if lattice.p.thermal else (1,)):
+                lattice.strip_waves = w
+                ty, ms = lattice.autotune_tile_y(candidates, steps)
+                if best is None or ms < best[2]:
+                    best = (ty, w, ms)
+            hit = best[:2]
+            self.table[self.key(lattice.p, device)] = {"tile_y": best[0], "strip_waves": best[1],
+                                                       "ms_per_step": best[2],
                                                        "candidates": list(candidates)}
             self._save()
-        else:
-            lattice.tile_y = ty
-        return ty
+        lattice.tile_y, lattice.strip_waves = hit
+        return hit
 
     def _save(self):
         d = os.path.dirname(self.path)

@@ -152,6 +152,15 @@ class Lattice:
     def tile_y(self, ty):
         check(lib().lbm_set_tile_y(self._ctx, int(ty)), self._ctx, "lbm_set_tile_y")
 
+    @property
+    def strip_waves(self):
+        """Waves per strip of the energy step (1 or 2; same results)."""
+        return lib().lbm_get_strip_waves(self._ctx)
+
+    @strip_waves.setter
+    def strip_waves(self, w):
+        check(lib().lbm_set_strip_waves(self._ctx, int(w)), self._ctx, "lbm_set_strip_waves")
+
     def autotune_tile_y(self, candidates=(2, 3, 4, 6, 8, 12, 16, 24, 32), steps=20):
         """Time each candidate strip height on this lattice and keep the
         fastest.  The state is saved first and restored afterwards, so the

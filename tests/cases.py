@@ -18,7 +18,7 @@ def oracle_params(c):
     return Params(**{k: c[k] for k in keys if k in c})
 
 
-def lib_params(c, precision=0, tile_y=0, rho_ref=None, xcd_remap=1):
+def lib_params(c, precision=0, tile_y=0, rho_ref=None, xcd_remap=1, strip_waves=0):
     from paper_2201_04560_amd import make_params
 
     scal = ["a", "sigma", "kappa", "s_rho", "s_e", "s_zeta", "s_j", "s_q", "eta_l", "eta_v",
@@ -30,6 +30,7 @@ def lib_params(c, precision=0, tile_y=0, rho_ref=None, xcd_remap=1):
     kw["precision"] = precision
     kw["tile_y"] = tile_y
     kw["xcd_remap"] = xcd_remap
+    kw["strip_waves"] = strip_waves
     kw["rho_ref"] = float(c.get("rho_v", 0.38) if rho_ref is None else rho_ref)
     return make_params(c["nx"], c["ny"], **kw)
 

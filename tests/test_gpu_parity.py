@@ -44,19 +44,23 @@ def _compare(lat, s, tol, what=""):
     return errs
 
 
-@pytest.mark.parametrize("nx,ny,walls,thermal,gy", [
-    (8, 6, False, False, 0.0),
-    (8, 6, False, True, 0.0),
-    (7, 8, True, True, 0.0),
-    (9, 7, True, True, -2e-3),
-    (61, 5, False, True, 0.0),
+@pytest.mark.parametrize("nx,ny,walls,thermal,gy,waves", [
+    (8, 6, False, False, 0.0, 1),
+    (8, 6, False, True, 0.0, 1),
+    (7, 8, True, True, 0.0, 1),
+    (9, 7, True, True, -2e-3, 1),
+    (61, 5, False, True, 0.0, 1),
+    (8, 6, False, True, 0.0, 2),
+    (9, 7, True, True, -2e-3, 2),
+    (61, 5, False, True, 0.0, 2),
 ])
-def test_one_step_random_state(nx, ny, walls, thermal, gy):
-    print(f"case one_step nx={nx} ny={ny} walls={walls} thermal={thermal} gy={gy}", flush=True)
+def test_one_step_random_state(nx, ny, walls, thermal, gy, waves):
+    print(f"case one_step nx={nx} ny={ny} walls={walls} thermal={thermal} gy={gy} waves={waves}",
+          flush=True)
     c, rho, ux, uy, T = cases.random_tiny(nx, ny, seed=nx * 100 + ny, walls=walls, thermal=thermal,
                                           gy=gy)
     s = _oracle(c, rho, ux, uy, T)
-    lat = _lat(c)
+    lat = _lat(c, strip_waves=waves)
     lat.init_fields(rho, ux, uy, T)
     _compare(lat, s, 1e-13, "init")
     s.step(1)
@@ -78,11 +82,12 @@ def test_droplet128_1000_steps_fp64():
     _compare(lat, s, 1e-10, "droplet128@1000")
 
 
-@pytest.mark.parametrize("tile_y", [2, 5, 16])
-def test_multi_tile_ragged_thermal_ring(tile_y):
+@pytest.mark.parametrize("tile_y,waves", [(2, 1), (5, 1), (16, 1), (2, 2), (5, 2), (16, 2)])
+def test_multi_tile_ragged_thermal_ring(tile_y, waves):
     """150 x 70: three 58-wide tiles with a ragged tail, several row
-    segments, Dirichlet ring as in the vaporisation workload."""
-    print(f"case ring150x70 tile_y={tile_y}", flush=True)
+    segments, Dirichlet ring as in the vaporisation workload; one and two
+    waves per strip."""
+    print(f"case ring150x70 tile_y={tile_y} waves={waves}", flush=True)
     eos, Tsat, rv, rl = cases.coexistence()
     Tout = 0.95 * eos.Tc
     nx, ny = 150, 70
@@ -92,17 +97,18 @@ def test_multi_tile_ragged_thermal_ring(tile_y):
              t_top_kind=np.full(nx, 1), t_top_val=np.full(nx, Tout), **cases.wl.DROPLET_RATES)
     rho, T = cases.wl.droplet(nx, ny, 20.0, 4.6 / 5.0, rl, rv, Tsat, Tout, seed=3)
     s = _oracle(c, rho, None, None, T)
-    lat = _lat(c, tile_y=tile_y)
+    lat = _lat(c, tile_y=tile_y, strip_waves=waves)
     lat.init_fields(rho, None, None, T)
     s.step(60)
     lat.step(60)
-    _compare(lat, s, 1e-11, f"ring tile_y={tile_y}")
+    _compare(lat, s, 1e-11, f"ring tile_y={tile_y} waves={waves}")
 
 
-def test_pool_walls_gravity_heater():
+@pytest.mark.parametrize("waves", [1, 2])
+def test_pool_walls_gravity_heater(waves):
     """Walls, psi-based wetting with a heater strip, gravity (rho_bar), mixed
     Dirichlet / adiabatic bottom, Dirichlet top."""
-    print("case pool 80x48", flush=True)
+    print(f"case pool 80x48 waves={waves}", flush=True)
     eos, Tsat, rv, rl = cases.coexistence()
     nx, ny = 80, 48
     kb = np.full(nx, 2)
@@ -117,7 +123,7 @@ def test_pool_walls_gravity_heater():
              t_top_val=np.full(nx, Tsat), **cases.wl.POOL_RATES)
     rho, T = cases.wl.pool(nx, ny, 30.0, 2.3, rl, rv, Tsat, seed_radius=6.0, seed=1)
     s = _oracle(c, rho, None, None, T)
-    lat = _lat(c, tile_y=8)
+    lat = _lat(c, tile_y=8, strip_waves=waves)
     lat.init_fields(rho, None, None, T)
     for n in (1, 49, 150):
         s.step(n)
@@ -126,13 +132,13 @@ def test_pool_walls_gravity_heater():
 
 
 def test_tile_shape_invariance_bitwise():
-    """Without gravity the result does not depend on the tiling or on the
-    XCD remap: identical bits."""
+    """Without gravity the result does not depend on the tiling, the XCD
+    remap or the waves per strip: identical bits."""
     print("case tile invariance", flush=True)
     c, rho, ux, uy, T = cases.random_tiny(130, 40, seed=5, walls=True, thermal=True)
     outs = []
-    for ty, rm in ((4, 1), (13, 0), (40, 1), (7, 0)):
-        lat = _lat(c, tile_y=ty, xcd_remap=rm)
+    for ty, rm, w in ((4, 1, 1), (13, 0, 1), (40, 1, 1), (7, 0, 1), (4, 1, 2), (13, 0, 2), (40, 1, 2)):
+        lat = _lat(c, tile_y=ty, xcd_remap=rm, strip_waves=w)
         lat.init_fields(rho, ux, uy, T)
         lat.step(7)
         outs.append(lat.populations())
