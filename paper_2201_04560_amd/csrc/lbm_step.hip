@@ -359,7 +359,7 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
   // MRT collision of one row from its inputs ci (pulled populations, jx, jy,
   // ux, uy, Fx, Fy, rho, rho - rho_ref, |F^m|^2/psi^2, Qxx + Qyy, Qxx - Qyy,
   // Qxy) in shifted moments n = M g (g = f - w rho_ref); stores the row
-  auto collide_store = [&](const int ys, const C (&ci)[kColl]) {
+  auto collide_store = [&](const int ys, const C (&ci)[kColl], const double rho_node) {
     const C* gp = ci;
     const C jxs = ci[9], jys = ci[10], ux = ci[11], uy = ci[12], Fx = ci[13], Fy = ci[14];
     const C rc = ci[15], sg = ci[16], fm2_ps2 = ci[17], qs = ci[18], qd = ci[19], qxyc = ci[20];
@@ -416,13 +416,13 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
 #pragma unroll
     for (int i = 0; i < 9; ++i) st(orow + i * plane_b, ox, S(o[i]));
     if (A.want_mass) {
-      // known-part density of the next step (walls: the populations
-      // leaving through a wall are replaced by those the closure will
-      // rebuild from the neighbour row)
-      double m = rref;
-#pragma unroll
-      for (int i = 0; i < 9; ++i) m += double(S(o[i]));
-      if (WALLS) {
+      // known-part density of the next step: the collision conserves mass
+      // (the populations leaving the node sum to its density up to the
+      // rounding of the stored values); at walls the populations leaving
+      // through the wall are replaced by those the closure will rebuild
+      // from the neighbour row
+      double m = rho_node;
+      if (WALLS && (ys <= 1 || ys >= ny - 2)) {
         const double dn = double(S(o[4])) + double(S(o[7])) + double(S(o[8])) + rref / 6.0;
         const double up = double(S(o[2])) + double(S(o[5])) + double(S(o[6])) + rref / 6.0;
         if (ys == 0) m -= dn;
@@ -523,7 +523,7 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
       ci[18] = C(qxx + qyy);
       ci[19] = C(qxx - qyy);
       ci[20] = C(qxy);
-      collide_store(ys, ci);
+      collide_store(ys, ci, rho);
     }
     if (MODE == MODE_MACRO && inseg) {
       const long long id = (long long)ys * nx + x;
