@@ -462,6 +462,9 @@ def main():
     ap.add_argument("--no-ladder", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--refinement-study", action="store_true",
+                    help="also run the Sec. 4.1 droplet refinement (meshes 128..432, float64, "
+                         "about 100 s of GPU time)")
     ap.add_argument("--pool-steps", type=int, default=5000,
                     help="steps of the 1024 x 2048 pool in the float32 accuracy check")
     ap.add_argument("--tile-cache", default=None, help="JSON cache of autotuned strip heights")
@@ -587,6 +590,17 @@ def main():
     if not args.no_adjoint:
         log("bench: adjoint 256x256, 500 steps")
         out["adjoint"] = optional_section(adjoint_bench)
+    if args.refinement_study:
+        from paper_2201_04560_amd.ladder import droplet_refinement
+
+        log("bench: droplet refinement study 128/192/288/432")
+        t0 = time.perf_counter()
+        rs = droplet_refinement((128, 192, 288, 432), L0=128, samples=200, sample0=2048,
+                                progress=lambda k, n: k % 20 == 0 and log(f"bench:   sample {k}/{n}"))
+        R = rs.pop("R")
+        rs["R_every_20_samples"] = np.round(R[:, ::20], 4).tolist()
+        rs["wall_s"] = round(time.perf_counter() - t0, 1)
+        out["refinement_study"] = rs
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(case)

@@ -105,3 +105,99 @@ class TileCache:
         with os.fdopen(fd, "w") as fh:
             json.dump(self.table, fh, indent=1, sort_keys=True)
         os.replace(tmp, self.path)
+
+
+# ----------------------------------------------------------------------------
+# droplet-vaporisation refinement study (Secs. 3 and 4.1)
+# ----------------------------------------------------------------------------
+def droplet_radius(rho, rho_l, rho_v):
+    """R = sqrt(A / pi) with A the liquid area: the smooth indicator
+    H = (1 + tanh((rho - rho_mid) / w)) / 2, rho_mid = (rho_l + rho_v) / 2,
+    w = (rho_l - rho_v) / 8, summed over the nodes.  (A clipped liquid
+    fraction (rho - rho_v) / (rho_l - rho_v) would sum to the total mass on a
+    periodic lattice, which the scheme conserves, and miss the interface.)"""
+    import numpy as np
+
+    mid, w = 0.5 * (rho_l + rho_v), (rho_l - rho_v) / 8.0
+    return float(np.sqrt((0.5 * (1.0 + np.tanh((rho - mid) / w))).sum() / np.pi))
+
+
+def droplet_mesh(L, L0=128, a0=6.12e-2, R0_frac=0.25, Tr=0.86, Tv_r=1.0, iso0=10000, cv=5.0,
+                 lam=2.0 / 3.0, eta=0.1, precision=0, tile_y=0):
+    """Mesh L of the droplet-vaporisation refinement (Sec. 4.1): L x L
+    periodic lattice, liquid disk of radius R0_frac L at T_sat = Tr T_c in
+    vapour at Tv_r T_c, temperature ring held at the vapour value; a, sigma,
+    kappa from the refinement rule with dx = L0 / L; the energy equation
+    starts after iso0 (L / L0)^2 steps.  Returns (params, boundary, rho, T,
+    level record)."""
+    import numpy as np
+
+    from .sim import make_params, refinement_level
+
+    dx = L0 / L
+    lv = refinement_level(a0, dx, Tr)
+    Tc, Ts = lv["Tc"], lv["T"]
+    Tv = Tv_r * Tc
+    rates = dict(s_rho=1.25, s_e=1.25, s_zeta=1.25, s_j=1.25, s_q=1.25)
+    p = make_params(L, L, a=lv["a"], sigma=lv["sigma"], kappa=lv["kappa"], rho_l=lv["rho_l"],
+                    rho_v=lv["rho_v"], thermal=1, n_iso=int(round(iso0 / dx ** 2)), cv=cv,
+                    lambda_l=lam, lambda_v=lam, eta_l=eta, eta_v=eta, t_side_dirichlet=1,
+                    t_side_val=Tv, rho_ref=lv["rho_v"], precision=precision, tile_y=tile_y, **rates)
+    bnd = dict(t_bottom_kind=np.full(L, 1, np.int32), t_bottom_val=np.full(L, Tv),
+               t_top_kind=np.full(L, 1, np.int32), t_top_val=np.full(L, Tv))
+    y, x = np.mgrid[0:L, 0:L].astype(np.float64)
+    d = np.hypot(x - L / 2 + 0.5, y - L / 2 + 0.5)
+    # Sec. 4.1 initial profile, width 4.6/5.0 on the base mesh (scaled with it)
+    t = np.tanh((4.6 / 5.0) * dx * (d - R0_frac * L))
+    rho = 0.5 * (lv["rho_v"] + lv["rho_l"]) - 0.5 * (lv["rho_l"] - lv["rho_v"]) * t
+    T = 0.5 * (Tv + Ts) - 0.5 * (Ts - Tv) * t
+    return p, bnd, rho, T, lv
+
+
+def droplet_refinement(meshes=(128, 192, 288, 432), L0=128, samples=200, sample0=2048,
+                       precision=0, progress=None, **kw):
+    """Run every mesh of the refinement in one batch (one multi-lattice
+    launch per step, graph-replayed), mesh L advanced sample0 (L / L0)^2
+    steps between samples of the droplet radius (the same physical times on
+    every mesh, Delta t ~ Delta x^2).  Returns the radius histories in base
+    mesh units, Delta*R between consecutive meshes (Eq. relative-change-R)
+    and the convergence orders log(Delta*_k / Delta*_k+1) / log(ratio)."""
+    import math
+
+    import numpy as np
+
+    from .sim import Batch, Lattice
+
+    lats, steps, levels = [], [], []
+    for L in meshes:
+        s = sample0 * (L / L0) ** 2
+        if abs(s - round(s)) > 1e-9:
+            raise ValueError("sample0 (L / L0)^2 must be an integer for every mesh")
+        p, bnd, rho, T, lv = droplet_mesh(L, L0, precision=precision, **kw)
+        lat = Lattice(p)
+        lat.set_boundary(**bnd)
+        lat.init_fields(rho, None, None, T)
+        lats.append(lat)
+        steps.append(int(round(s)))
+        levels.append(lv)
+    R = np.zeros((len(meshes), samples + 1))
+    for m, (lat, lv) in enumerate(zip(lats, levels)):
+        R[m, 0] = droplet_radius(lat.fields()[0], lv["rho_l"], lv["rho_v"]) * L0 / meshes[m]
+    b = Batch(lats)
+    for k in range(1, samples + 1):
+        b.run(steps)
+        for m, (lat, lv) in enumerate(zip(lats, levels)):
+            R[m, k] = droplet_radius(lat.fields()[0], lv["rho_l"], lv["rho_v"]) * L0 / meshes[m]
+        if progress:
+            progress(k, samples)
+    b.close()
+    for lat in lats:
+        lat.close()
+    dstar = [float(np.abs(R[m] - R[m + 1]).sum() / np.abs(R[m + 1]).sum())
+             for m in range(len(meshes) - 1)]
+    ratio = meshes[1] / meshes[0]
+    orders = [math.log(dstar[m] / dstar[m + 1]) / math.log(ratio) for m in range(len(dstar) - 1)]
+    return {"meshes": list(meshes), "steps_per_sample": steps, "samples": samples, "R": R,
+            "delta_star_R": dstar, "orders": orders,
+            "kappa": [lv["kappa"] for lv in levels], "sigma": [lv["sigma"] for lv in levels],
+            "a": [lv["a"] for lv in levels]}

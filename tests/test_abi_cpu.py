@@ -168,3 +168,19 @@ def test_adjoint_bytes_and_scope(lib):
         q = pp.make_params(64, 64, **{**dict(thermal=1), **kw})
         assert lib.lbm_adjoint_bytes(ctypes.byref(q), 10, 5, ctypes.byref(n1)) == 6
     assert lib.lbm_adjoint_bytes(ctypes.byref(p), 0, 5, ctypes.byref(n1)) == 1
+
+
+def test_droplet_refinement_meshes_match_table_2(lib):
+    """Meshes of the Sec. 4.1 refinement from the product's rules: sigma
+    reproduces Table 2's column, a scales with dx^2, the isothermal start
+    with dx^-2, and the initial state has the Maxwell densities."""
+    from paper_2201_04560_amd.ladder import droplet_mesh, droplet_radius
+
+    printed_sigma = {128: 0.103, 192: 0.115, 288: 0.121, 432: 0.123}
+    for L, s in printed_sigma.items():
+        p, bnd, rho, T, lv = droplet_mesh(L)
+        assert abs(p.sigma - s) <= 5e-4
+        assert abs(p.a / 6.12e-2 - (128 / L) ** 2) < 1e-14
+        assert p.n_iso == round(10000 * (L / 128) ** 2)
+        assert abs(rho.max() - lv["rho_l"]) < 1e-6 and abs(rho.min() - lv["rho_v"]) < 1e-6
+        assert abs(droplet_radius(rho, lv["rho_l"], lv["rho_v"]) - L / 4) < 0.05 * L / 4
