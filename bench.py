@@ -465,6 +465,9 @@ def main():
     ap.add_argument("--refinement-study", action="store_true",
                     help="also run the Sec. 4.1 droplet refinement (meshes 128..432, float64, "
                          "about 100 s of GPU time)")
+    ap.add_argument("--pool-refinement-study", action="store_true",
+                    help="also run the Sec. 4.3 pool refinement (meshes 160..540, 40000 base "
+                         "steps, rho_wh 0.38, T_h 1.2 T_c, float64, about 25 s of GPU time)")
     ap.add_argument("--pool-steps", type=int, default=5000,
                     help="steps of the 1024 x 2048 pool in the float32 accuracy check")
     ap.add_argument("--tile-cache", default=None, help="JSON cache of autotuned strip heights")
@@ -601,6 +604,17 @@ def main():
         rs["R_every_20_samples"] = np.round(R[:, ::20], 4).tolist()
         rs["wall_s"] = round(time.perf_counter() - t0, 1)
         out["refinement_study"] = rs
+    if args.pool_refinement_study:
+        from paper_2201_04560_amd.ladder import pool_refinement
+
+        log("bench: pool refinement study 160/240/360/540")
+        t0 = time.perf_counter()
+        ps = pool_refinement(rho_wh=0.38, Th_r=1.2,
+                             progress=lambda k, n: k % 20 == 0 and log(f"bench:   sample {k}/{n}"))
+        for k in ("d_rho", "d_T"):
+            ps[k] = np.round(np.asarray(ps[k])[:, ::8], 5).tolist()
+        ps["wall_s"] = round(time.perf_counter() - t0, 1)
+        out["pool_refinement_study"] = ps
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(case)

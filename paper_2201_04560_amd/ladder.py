@@ -201,3 +201,185 @@ def droplet_refinement(meshes=(128, 192, 288, 432), L0=128, samples=200, sample0
             "delta_star_R": dstar, "orders": orders,
             "kappa": [lv["kappa"] for lv in levels], "sigma": [lv["sigma"] for lv in levels],
             "a": [lv["a"] for lv in levels]}
+
+
+# ----------------------------------------------------------------------------
+# pool-boiling refinement: space / space-time differences between meshes
+# and the time-shift synchronisation (Sec. 4.3)
+# ----------------------------------------------------------------------------
+def pool_mesh(N, N0=160, a0=6.12e-2, Tr=0.86, Th_r=1.0, rho_wh=3.44, heater_frac=0.125,
+              gy0=-2.5e-5, cv=5.0, lambda_l=1.95, lambda_v=0.114, eta=0.1, precision=0, tile_y=0):
+    """Mesh N (N x N) of the Sec. 4.3 pool: periodic sides, Zou-He walls,
+    liquid below half the height at T_sat = Tr T_c, top wall at T_sat with
+    wall density 0.38, bottom wall at T_sat with wall density 6.50 except the
+    centred heater (heater_frac N nodes) at Th_r T_c with density rho_wh;
+    a, sigma, kappa and g by the refinement rules with dx = N0 / N.
+    Returns (params, boundary, rho, T, level record)."""
+    import numpy as np
+
+    from .sim import make_params, refinement_level
+
+    dx = N0 / N
+    lv = refinement_level(a0, dx, Tr, 0.0, gy0)
+    Tc, Ts = lv["Tc"], lv["T"]
+    rates = dict(s_rho=1.0, s_e=0.8, s_zeta=0.8, s_j=1.0, s_q=1.1)
+    p = make_params(N, N, a=lv["a"], sigma=lv["sigma"], kappa=lv["kappa"], rho_l=lv["rho_l"],
+                    rho_v=lv["rho_v"], walls=1, thermal=1, gy=lv["gy"], cv=cv, lambda_l=lambda_l,
+                    lambda_v=lambda_v, eta_l=eta, eta_v=eta, rho_ref=lv["rho_v"],
+                    precision=precision, tile_y=tile_y, **rates)
+    hw = max(1, int(round(heater_frac * N)))
+    h0 = N // 2 - hw // 2
+    tb = np.full(N, Ts)
+    tb[h0:h0 + hw] = Th_r * Tc
+    rwb = np.full(N, 6.50)
+    rwb[h0:h0 + hw] = rho_wh
+    bnd = dict(rho_w_bottom=rwb, rho_w_top=0.38, t_bottom_kind=np.full(N, 1, np.int32),
+               t_bottom_val=tb, t_top_kind=np.full(N, 1, np.int32), t_top_val=Ts)
+    y = (np.arange(N, dtype=np.float64)[:, None] + 0.5) * np.ones((1, N))
+    # Eq. boundary-cond: liquid below half the height (smoothed over one
+    # base-mesh node)
+    t = np.tanh((y - N / 2) * dx)
+    rho = 0.5 * (lv["rho_l"] + lv["rho_v"]) - 0.5 * (lv["rho_l"] - lv["rho_v"]) * t
+    T = np.full((N, N), Ts)
+    return p, bnd, rho, T, lv
+
+
+def bilinear(coarse, n_fine, periodic_x=True):
+    """Coarse node-centred field [Nc, Nc'] interpolated linearly onto the
+    node centres of the fine mesh [n_fine, n_fine'] covering the same domain
+    (periodic in x, clamped in y)."""
+    import numpy as np
+
+    ncy, ncx = coarse.shape
+    nfy, nfx = (n_fine, n_fine) if np.isscalar(n_fine) else n_fine
+    yc = (np.arange(nfy) + 0.5) * ncy / nfy - 0.5
+    xc = (np.arange(nfx) + 0.5) * ncx / nfx - 0.5
+    yc = np.clip(yc, 0.0, ncy - 1.0)
+    y0 = np.minimum(np.floor(yc).astype(int), ncy - 2)
+    fy = yc - y0
+    x0 = np.floor(xc).astype(int)
+    fx = xc - x0
+    xa, xb = x0 % ncx, (x0 + 1) % ncx
+    if not periodic_x:
+        xa, xb = np.clip(x0, 0, ncx - 1), np.clip(x0 + 1, 0, ncx - 1)
+    c = coarse
+    top = c[y0][:, xa] * (1 - fx) + c[y0][:, xb] * fx
+    bot = c[y0 + 1][:, xa] * (1 - fx) + c[y0 + 1][:, xb] * fx
+    return top * (1 - fy)[:, None] + bot * fy[:, None]
+
+
+def space_difference(coarse, fine):
+    """Eq. rel-diff-timestep: sum |I(coarse) - fine| / sum |fine|."""
+    import numpy as np
+
+    i = bilinear(coarse, fine.shape)
+    return float(np.abs(i - fine).sum() / np.abs(fine).sum())
+
+
+def best_shift(series_coarse, fine_ref, shifts):
+    """Eq. rel-diff-minimize: the shift whose coarse field (interpolated)
+    differs least, in L1, from the finest field at the reference time.
+    series_coarse maps shift -> field."""
+    import numpy as np
+
+    best, arg = None, None
+    for d in shifts:
+        v = np.abs(bilinear(series_coarse[d], fine_ref.shape) - fine_ref).sum()
+        if best is None or v < best:
+            best, arg = v, d
+    return arg
+
+
+def pool_refinement(meshes=(160, 240, 360, 540), N0=160, steps0=40000, every0=640, tau0=5120,
+                    m0=4800, shift_every0=320, precision=0, progress=None, **kw):
+    """Sec. 4.3 study: every mesh in one batch, rho and T sampled every
+    every0 base-mesh steps (the same physical times on every mesh), and
+    every shift_every0 steps in [tau0 - m0, tau0 + m0].  Returns the space
+    differences d^N(t) of rho and T between consecutive meshes, the global
+    differences D^N and their convergence orders, the time shifts delta of
+    every coarser mesh against the finest at tau0, and the shifted global
+    differences (Eqs. rel-diff-timestep to rel-diff-minimize)."""
+    import math
+
+    import numpy as np
+
+    from .sim import Batch, Lattice
+
+    # mesh N advances (N / N0)^2 steps per base step: every sampling interval
+    # must be a whole number of steps on every mesh
+    for v in (steps0, every0, tau0, m0, shift_every0):
+        for N in meshes:
+            s = v * (N / N0) ** 2
+            if abs(s - round(s)) > 1e-9:
+                raise ValueError(f"{v} base steps are not a whole number of steps on mesh {N}")
+    times = sorted(set(range(0, steps0 + 1, every0)) |
+                   set(range(tau0 - m0, tau0 + m0 + 1, shift_every0)))
+    lats, levels = [], []
+    for N in meshes:
+        p, bnd, rho, T, lv = pool_mesh(N, N0, precision=precision, **kw)
+        lat = Lattice(p)
+        lat.set_boundary(**bnd)
+        lat.init_fields(rho, None, None, T)
+        lats.append(lat)
+        levels.append(lv)
+    fields = {}  # (mesh index, base time) -> (rho, T/T_c) float32
+    def sample(t):
+        for m, (lat, lv) in enumerate(zip(lats, levels)):
+            r, _, _, T = lat.fields()
+            fields[(m, t)] = (r.astype(np.float32), (T / lv["Tc"]).astype(np.float32))
+    sample(0)
+    b = Batch(lats)
+    prev = 0
+    for k, t in enumerate(times[1:], 1):
+        b.run([int(round((t - prev) * (N / N0) ** 2)) for N in meshes])
+        sample(t)
+        prev = t
+        if progress:
+            progress(k, len(times) - 1)
+    b.close()
+    for lat in lats:
+        lat.close()
+    grid = list(range(0, steps0 + 1, every0))
+    nm = len(meshes)
+    out = {"meshes": list(meshes), "steps0": steps0, "every0": every0,
+           "kappa": [lv["kappa"] for lv in levels], "sigma": [lv["sigma"] for lv in levels]}
+    ratio = meshes[1] / meshes[0]
+    for fi, name in ((0, "rho"), (1, "T")):
+        d = [[space_difference(fields[(m, t)][fi], fields[(m + 1, t)][fi]) for t in grid]
+             for m in range(nm - 1)]
+        D = []
+        for m in range(nm - 1):
+            num = sum(np.abs(bilinear(fields[(m, t)][fi], fields[(m + 1, t)][fi].shape) -
+                             fields[(m + 1, t)][fi]).sum() for t in grid)
+            den = sum(np.abs(fields[(m + 1, t)][fi]).sum() for t in grid)
+            D.append(float(num / den))
+        out[f"d_{name}"] = d
+        out[f"D_{name}"] = D
+        out[f"orders_{name}"] = [math.log(D[m] / D[m + 1]) / math.log(ratio) for m in range(nm - 2)]
+    # time shifts against the finest mesh at tau0 (density field)
+    shifts = list(range(-m0, m0 + 1, shift_every0))
+    fine = fields[(nm - 1, tau0)][0]
+    delta = []
+    for m in range(nm - 1):
+        series = {s: fields[(m, tau0 + s)][0] for s in shifts}
+        delta.append(best_shift(series, fine, shifts))
+    delta.append(0)
+    out["delta"] = delta
+    # shifted global differences: times t (1 + delta / tau0), nearest sample
+    avail = sorted(t for (mm, t) in fields if mm == 0)
+    def near(t):
+        return min(avail, key=lambda a: abs(a - t))
+    for fi, name in ((0, "rho"), (1, "T")):
+        Ds = []
+        for m in range(nm - 1):
+            num = den = 0.0
+            for t in grid:
+                tc, tf = near(t * (1 + delta[m] / tau0)), near(t * (1 + delta[m + 1] / tau0))
+                a, f = fields[(m, tc)][fi], fields[(m + 1, tf)][fi]
+                num += np.abs(bilinear(a, f.shape) - f).sum()
+                den += np.abs(f).sum()
+            Ds.append(float(num / den))
+        out[f"D_shifted_{name}"] = Ds
+        out[f"orders_shifted_{name}"] = [math.log(Ds[m] / Ds[m + 1]) / math.log(ratio)
+                                         for m in range(nm - 2)]
+    return out

@@ -146,3 +146,24 @@ def test_droplet_refinement_converges():
     d = r["delta_star_R"]
     assert d[1] < d[0] < 1e-2
     assert r["orders"][0] > 1.5
+
+
+def test_pool_refinement_converges():
+    """Sec. 4.3 differences between meshes on a small pool (64, 96, 144 over a
+    64 base; a, sigma, kappa and g by the refinement rules): the global
+    differences fall with refinement, the time shifts stay inside the search
+    window and shrink towards the finest mesh."""
+    print("case pool refinement 64/96/144", flush=True)
+    from paper_2201_04560_amd.ladder import pool_refinement
+
+    r = pool_refinement((64, 96, 144), N0=64, steps0=6400, every0=320, tau0=1280, m0=960,
+                        shift_every0=160, rho_wh=0.38, Th_r=1.2)
+    print({k: v for k, v in r.items() if not k.startswith("d_")}, flush=True)
+    for k in ("D_rho", "D_T", "D_shifted_rho", "D_shifted_T"):
+        assert all(np.isfinite(r[k])) and all(0 < v < 0.5 for v in r[k]), k
+    assert r["D_rho"][1] < r["D_rho"][0]
+    assert r["D_T"][1] < r["D_T"][0]
+    assert all(abs(d) < 960 for d in r["delta"]) and r["delta"][-1] == 0
+    assert abs(r["delta"][1]) <= abs(r["delta"][0])
+    # one space difference per sample time and mesh pair
+    assert len(r["d_rho"]) == 2 and len(r["d_rho"][0]) == 6400 // 320 + 1

@@ -1,0 +1,66 @@
+"""Host-side pieces of the refinement studies (Sec. 4): the coarse-to-fine
+interpolation, the relative differences and the time-shift search, against
+closed forms; the mesh set-ups against the refinement rules."""
+import numpy as np
+
+from paper_2201_04560_amd.ladder import (best_shift, bilinear, droplet_radius, pool_mesh,
+                                         space_difference)
+
+
+def test_bilinear_reproduces_linear_and_constant_fields():
+    nc, nf = 16, 24
+    yc = (np.arange(nc) + 0.5) / nc
+    yf = (np.arange(nf) + 0.5) / nf
+    c = np.repeat((3.0 * yc - 1.0)[:, None], nc, axis=1)
+    i = bilinear(c, nf)
+    exact = np.repeat((3.0 * yf - 1.0)[:, None], nf, axis=1)
+    # rows beyond the outermost coarse node centres are clamped
+    inner = (yf > yc[0]) & (yf < yc[-1])
+    assert np.abs(i - exact)[inner].max() < 1e-14
+    assert np.abs(bilinear(np.full((nc, nc), 2.5), nf) - 2.5).max() < 1e-15
+
+
+def test_bilinear_is_periodic_in_x():
+    nc, nf = 12, 18
+    xc = 2 * np.pi * (np.arange(nc) + 0.5) / nc
+    xf = 2 * np.pi * (np.arange(nf) + 0.5) / nf
+    c = np.repeat(np.cos(xc)[None, :], 4, axis=0)
+    i = bilinear(c, (6, nf))
+    # linear interpolation of cos on a 12-point grid: error below (dx^2 / 8)
+    assert np.abs(i - np.cos(xf)[None, :]).max() < (2 * np.pi / nc) ** 2 / 8 + 1e-12
+
+
+def test_space_difference_and_shift_search():
+    n = 32
+    y, x = np.mgrid[0:n, 0:n] + 0.5
+    front = lambda t: 1.0 + np.tanh((y - 10.0 - 0.01 * t) / 2.0)
+    fine = front(600.0)
+    assert space_difference(fine, fine) == 0.0
+    series = {s: front(600.0 + s) for s in range(-500, 501, 100)}
+    assert best_shift(series, fine, list(series)) == 0
+    series = {s: front(400.0 + s) for s in range(-500, 501, 100)}
+    assert best_shift(series, fine, list(series)) == 200
+
+
+def test_pool_meshes_follow_the_refinement_rules():
+    base = pool_mesh(160)
+    for N in (160, 240, 360, 540):
+        p, bnd, rho, T, lv = pool_mesh(N)
+        dx = 160 / N
+        assert abs(p.a / base[0].a - dx ** 2) < 1e-14
+        assert abs(p.gy / base[0].gy - dx ** 3) < 1e-14
+        hw = int(round(0.125 * N))
+        assert (bnd["t_bottom_val"] > lv["T"]).sum() == hw
+        assert (bnd["rho_w_bottom"] == 3.44).sum() == hw
+        # liquid below half the height, a smooth interface a few base nodes wide
+        assert np.abs(rho[:4] - lv["rho_l"]).max() < 1e-9
+        assert np.abs(rho[-4:] - lv["rho_v"]).max() < 1e-9
+        assert abs(rho[N // 2 - 1, 0] + rho[N // 2, 0] - lv["rho_l"] - lv["rho_v"]) < 1e-12
+
+
+def test_droplet_radius_of_a_disk():
+    n = 200
+    y, x = np.mgrid[0:n, 0:n] + 0.5
+    d = np.hypot(x - n / 2, y - n / 2)
+    rho = 3.44 - 3.06 * np.tanh(d - 40.0)
+    assert abs(droplet_radius(rho, 6.5, 0.38) - 40.0) < 0.1
