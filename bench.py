@@ -467,7 +467,7 @@ def main():
                          "about 100 s of GPU time)")
     ap.add_argument("--pool-refinement-study", action="store_true",
                     help="also run the Sec. 4.3 pool refinement (meshes 160..540, 40000 base "
-                         "steps, rho_wh 0.38, T_h 1.2 T_c, float64, about 25 s of GPU time)")
+                         "steps, rho_wh 0.38, T_h 1.2 T_c, float64, about 40 s of GPU time)")
     ap.add_argument("--pool-steps", type=int, default=5000,
                     help="steps of the 1024 x 2048 pool in the float32 accuracy check")
     ap.add_argument("--tile-cache", default=None, help="JSON cache of autotuned strip heights")
@@ -610,7 +610,7 @@ def main():
         log("bench: pool refinement study 160/240/360/540")
         t0 = time.perf_counter()
         ps = pool_refinement(rho_wh=0.38, Th_r=1.2,
-                             progress=lambda k, n: k % 20 == 0 and log(f"bench:   sample {k}/{n}"))
+                             progress=lambda k, n, what: k % 20 == 0 and log(f"bench:   {what} sample {k}/{n}"))
         for k in ("d_rho", "d_T"):
             ps[k] = np.round(np.asarray(ps[k])[:, ::8], 5).tolist()
         ps["wall_s"] = round(time.perf_counter() - t0, 1)

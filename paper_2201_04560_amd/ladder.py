@@ -207,7 +207,7 @@ def droplet_refinement(meshes=(128, 192, 288, 432), L0=128, samples=200, sample0
 # pool-boiling refinement: space / space-time differences between meshes
 # and the time-shift synchronisation (Sec. 4.3)
 # ----------------------------------------------------------------------------
-def pool_mesh(N, N0=160, a0=6.12e-2, Tr=0.86, Th_r=1.0, rho_wh=3.44, heater_frac=0.125,
+def pool_mesh(N, N0=160, a0=6.12e-2, Tr=0.86, Th_r=1.0, rho_wh=3.44, heater_frac=0.05,
               gy0=-2.5e-5, cv=5.0, lambda_l=1.95, lambda_v=0.114, eta=0.1, precision=0, tile_y=0):
     """Mesh N (N x N) of the Sec. 4.3 pool: periodic sides, Zou-He walls,
     liquid below half the height at T_sat = Tr T_c, top wall at T_sat with
@@ -292,94 +292,130 @@ def best_shift(series_coarse, fine_ref, shifts):
 
 def pool_refinement(meshes=(160, 240, 360, 540), N0=160, steps0=40000, every0=640, tau0=5120,
                     m0=4800, shift_every0=320, precision=0, progress=None, **kw):
-    """Sec. 4.3 study: every mesh in one batch, rho and T sampled every
-    every0 base-mesh steps (the same physical times on every mesh), and
-    every shift_every0 steps in [tau0 - m0, tau0 + m0].  Returns the space
-    differences d^N(t) of rho and T between consecutive meshes, the global
-    differences D^N and their convergence orders, the time shifts delta of
-    every coarser mesh against the finest at tau0, and the shifted global
-    differences (Eqs. rel-diff-timestep to rel-diff-minimize)."""
+    """Sec. 4.3 study, every mesh in one batch.  Pass 1 samples rho and T
+    every every0 base-mesh steps (the same physical times on every mesh)
+    and every shift_every0 steps in [tau0 - m0, tau0 + m0]; it gives the
+    space differences d^N(t) of rho and T between consecutive meshes
+    (Eq. rel-diff-timestep), the global differences D^N (Eq.
+    global-rel-diff) with their convergence orders, and the time shift
+    delta of every coarser mesh against the finest at tau0 (Eq.
+    rel-diff-minimize).  Pass 2 reruns the coarser meshes with a non-zero
+    shift and samples them at the shifted times t_k (1 + delta / tau0),
+    rounded to whole steps of each mesh, for the shifted global differences
+    (Eq. global-rel-diff-shifted).  Also returned: the heat flux Q(t) of
+    Eq. pool-heat-flux per mesh (re-scaled to the base mesh), the relative
+    differences of consecutive Q curves over t > 0 and their orders, and
+    the vapour area under the initial interface (bubble growth and
+    departure)."""
     import math
 
     import numpy as np
 
     from .sim import Batch, Lattice
 
-    # mesh N advances (N / N0)^2 steps per base step: every sampling interval
-    # must be a whole number of steps on every mesh
+    ratios = [(N / N0) ** 2 for N in meshes]  # steps of mesh N per base step
     for v in (steps0, every0, tau0, m0, shift_every0):
-        for N in meshes:
-            s = v * (N / N0) ** 2
-            if abs(s - round(s)) > 1e-9:
+        for N, q in zip(meshes, ratios):
+            if abs(v * q - round(v * q)) > 1e-9:
                 raise ValueError(f"{v} base steps are not a whole number of steps on mesh {N}")
+    if tau0 + m0 > steps0 or tau0 - m0 < 0:
+        raise ValueError("the shift window must lie inside the run")
+    nm = len(meshes)
+
+    def build(idx):
+        lats, levels = [], []
+        for m in idx:
+            p, bnd, rho, T, lv = pool_mesh(meshes[m], N0, precision=precision, **kw)
+            lat = Lattice(p)
+            lat.set_boundary(**bnd)
+            lat.init_fields(rho, None, None, T)
+            lats.append(lat)
+            levels.append(lv)
+        return lats, levels
+
+    def march(idx, targets, take, label):
+        """Advance meshes idx through the per-mesh step counts targets[j]
+        (one row per event) and call take(j, event, lattice, level) at each."""
+        lats, levels = build(idx)
+        for j, (lat, lv) in enumerate(zip(lats, levels)):
+            take(j, 0, lat, lv)
+        b = Batch(lats)
+        done = [0] * len(idx)
+        for e in range(1, len(targets)):
+            b.run([targets[e][j] - done[j] for j in range(len(idx))])
+            done = list(targets[e])
+            for j, (lat, lv) in enumerate(zip(lats, levels)):
+                take(j, e, lat, lv)
+            if progress:
+                progress(e, len(targets) - 1, label)
+        b.close()
+        for lat in lats:
+            lat.close()
+        return levels
+
+    fields, flux = {}, {}  # (mesh, base time) -> (rho, T / T_c); -> Q
+    Tc0 = [None]
     times = sorted(set(range(0, steps0 + 1, every0)) |
                    set(range(tau0 - m0, tau0 + m0 + 1, shift_every0)))
-    lats, levels = [], []
-    for N in meshes:
-        p, bnd, rho, T, lv = pool_mesh(N, N0, precision=precision, **kw)
-        lat = Lattice(p)
-        lat.set_boundary(**bnd)
-        lat.init_fields(rho, None, None, T)
-        lats.append(lat)
-        levels.append(lv)
-    fields = {}  # (mesh index, base time) -> (rho, T/T_c) float32
-    def sample(t):
-        for m, (lat, lv) in enumerate(zip(lats, levels)):
-            r, _, _, T = lat.fields()
-            fields[(m, t)] = (r.astype(np.float32), (T / lv["Tc"]).astype(np.float32))
-    sample(0)
-    b = Batch(lats)
-    prev = 0
-    for k, t in enumerate(times[1:], 1):
-        b.run([int(round((t - prev) * (N / N0) ** 2)) for N in meshes])
-        sample(t)
-        prev = t
-        if progress:
-            progress(k, len(times) - 1)
-    b.close()
-    for lat in lats:
-        lat.close()
+
+    def take1(m, e, lat, lv):
+        r, _, _, T = lat.fields()
+        t = times[e]
+        fields[(m, t)] = (r.astype(np.float32), (T / lv["Tc"]).astype(np.float32))
+        # lattice units: T scales with T_c(a) ~ dx^2 and d/dy with 1/dx
+        if Tc0[0] is None:
+            Tc0[0] = lv["Tc"] / (N0 / meshes[0]) ** 2
+        flux[(m, t)] = lat.norms()["q_bottom"] * Tc0[0] / (lv["Tc"] * (N0 / meshes[m]))
+
+    levels = march(list(range(nm)), [[int(round(t * q)) for q in ratios] for t in times], take1,
+                   "pass 1")
     grid = list(range(0, steps0 + 1, every0))
-    nm = len(meshes)
-    out = {"meshes": list(meshes), "steps0": steps0, "every0": every0,
+    out = {"meshes": list(meshes), "steps0": steps0, "every0": every0, "t": grid,
            "kappa": [lv["kappa"] for lv in levels], "sigma": [lv["sigma"] for lv in levels]}
     ratio = meshes[1] / meshes[0]
+
+    def orders(D):
+        return [math.log(D[m] / D[m + 1]) / math.log(ratio) for m in range(len(D) - 1)]
+
+    def interp_diff(a, f):
+        return float(np.abs(bilinear(a, f.shape) - f).sum())
+
     for fi, name in ((0, "rho"), (1, "T")):
-        d = [[space_difference(fields[(m, t)][fi], fields[(m + 1, t)][fi]) for t in grid]
-             for m in range(nm - 1)]
-        D = []
-        for m in range(nm - 1):
-            num = sum(np.abs(bilinear(fields[(m, t)][fi], fields[(m + 1, t)][fi].shape) -
-                             fields[(m + 1, t)][fi]).sum() for t in grid)
-            den = sum(np.abs(fields[(m + 1, t)][fi]).sum() for t in grid)
-            D.append(float(num / den))
-        out[f"d_{name}"] = d
+        out[f"d_{name}"] = [[space_difference(fields[(m, t)][fi], fields[(m + 1, t)][fi]) for t in grid]
+                            for m in range(nm - 1)]
+        D = [sum(interp_diff(fields[(m, t)][fi], fields[(m + 1, t)][fi]) for t in grid) /
+             sum(float(np.abs(fields[(m + 1, t)][fi]).sum()) for t in grid) for m in range(nm - 1)]
         out[f"D_{name}"] = D
-        out[f"orders_{name}"] = [math.log(D[m] / D[m + 1]) / math.log(ratio) for m in range(nm - 2)]
-    # time shifts against the finest mesh at tau0 (density field)
+        out[f"orders_{name}"] = orders(D)
+    # heat flux: t = 0 is left out (a temperature jump at the heater edge,
+    # whose one-sided gradient grows as 1 / dx)
+    Q = np.array([[flux[(m, t)] for t in grid] for m in range(nm)])
+    DQ = [float(np.abs(Q[m, 1:] - Q[m + 1, 1:]).sum() / np.abs(Q[m + 1, 1:]).sum()) for m in range(nm - 1)]
+    out["Q"] = Q.tolist()
+    out["D_Q"] = DQ
+    out["orders_Q"] = orders(DQ)
+    out["bubble_area"] = [[float((fields[(m, t)][0][:meshes[m] // 2 - 2] <
+                                  0.5 * (levels[m]["rho_l"] + levels[m]["rho_v"])).sum()
+                                 * (N0 / meshes[m]) ** 2) for t in grid] for m in range(nm)]
+    # Eq. rel-diff-minimize on the density field
     shifts = list(range(-m0, m0 + 1, shift_every0))
     fine = fields[(nm - 1, tau0)][0]
-    delta = []
-    for m in range(nm - 1):
-        series = {s: fields[(m, tau0 + s)][0] for s in shifts}
-        delta.append(best_shift(series, fine, shifts))
-    delta.append(0)
+    delta = [best_shift({d: fields[(m, tau0 + d)][0] for d in shifts}, fine, shifts)
+             for m in range(nm - 1)] + [0]
     out["delta"] = delta
-    # shifted global differences: times t (1 + delta / tau0), nearest sample
-    avail = sorted(t for (mm, t) in fields if mm == 0)
-    def near(t):
-        return min(avail, key=lambda a: abs(a - t))
+    # pass 2: shifted samples of every coarser mesh with delta != 0
+    shifted = {m: {t: fields[(m, t)] for t in grid} for m in range(nm) if delta[m] == 0}
+    redo = [m for m in range(nm) if delta[m] != 0]
+    if redo:
+        def take2(j, e, lat, lv):
+            r, _, _, T = lat.fields()
+            shifted.setdefault(redo[j], {})[grid[e]] = (r.astype(np.float32),
+                                                        (T / lv["Tc"]).astype(np.float32))
+        targets = [[int(round(t * (1 + delta[m] / tau0) * ratios[m])) for m in redo] for t in grid]
+        march(redo, targets, take2, "pass 2")
     for fi, name in ((0, "rho"), (1, "T")):
-        Ds = []
-        for m in range(nm - 1):
-            num = den = 0.0
-            for t in grid:
-                tc, tf = near(t * (1 + delta[m] / tau0)), near(t * (1 + delta[m + 1] / tau0))
-                a, f = fields[(m, tc)][fi], fields[(m + 1, tf)][fi]
-                num += np.abs(bilinear(a, f.shape) - f).sum()
-                den += np.abs(f).sum()
-            Ds.append(float(num / den))
+        Ds = [sum(interp_diff(shifted[m][t][fi], shifted[m + 1][t][fi]) for t in grid) /
+              sum(float(np.abs(shifted[m + 1][t][fi]).sum()) for t in grid) for m in range(nm - 1)]
         out[f"D_shifted_{name}"] = Ds
-        out[f"orders_shifted_{name}"] = [math.log(Ds[m] / Ds[m + 1]) / math.log(ratio)
-                                         for m in range(nm - 2)]
+        out[f"orders_shifted_{name}"] = orders(Ds)
     return out

@@ -150,14 +150,14 @@ def test_droplet_refinement_converges():
 
 def test_pool_refinement_converges():
     """Sec. 4.3 differences between meshes on a small pool (64, 96, 144 over a
-    64 base; a, sigma, kappa and g by the refinement rules): the global
-    differences fall with refinement, the time shifts stay inside the search
-    window and shrink towards the finest mesh."""
+    64 base, heater N/8 wide; a, sigma, kappa and g by the refinement rules):
+    the global differences fall with refinement, the time shifts stay inside
+    the search window and shrink towards the finest mesh."""
     print("case pool refinement 64/96/144", flush=True)
     from paper_2201_04560_amd.ladder import pool_refinement
 
     r = pool_refinement((64, 96, 144), N0=64, steps0=6400, every0=320, tau0=1280, m0=960,
-                        shift_every0=160, rho_wh=0.38, Th_r=1.2)
+                        shift_every0=160, rho_wh=0.38, Th_r=1.2, heater_frac=0.125)
     print({k: v for k, v in r.items() if not k.startswith("d_")}, flush=True)
     for k in ("D_rho", "D_T", "D_shifted_rho", "D_shifted_T"):
         assert all(np.isfinite(r[k])) and all(0 < v < 0.5 for v in r[k]), k

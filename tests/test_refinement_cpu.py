@@ -49,7 +49,7 @@ def test_pool_meshes_follow_the_refinement_rules():
         dx = 160 / N
         assert abs(p.a / base[0].a - dx ** 2) < 1e-14
         assert abs(p.gy / base[0].gy - dx ** 3) < 1e-14
-        hw = int(round(0.125 * N))
+        hw = int(round(0.05 * N))
         assert (bnd["t_bottom_val"] > lv["T"]).sum() == hw
         assert (bnd["rho_w_bottom"] == 3.44).sum() == hw
         # liquid below half the height, a smooth interface a few base nodes wide
@@ -64,3 +64,17 @@ def test_droplet_radius_of_a_disk():
     d = np.hypot(x - n / 2, y - n / 2)
     rho = 3.44 - 3.06 * np.tanh(d - 40.0)
     assert abs(droplet_radius(rho, 6.5, 0.38) - 40.0) < 0.1
+
+
+def test_pool_refinement_rejects_fractional_intervals():
+    import pytest
+
+    from paper_2201_04560_amd.ladder import pool_refinement
+
+    # 100 base steps are 225 steps on 240 but 506.25 on 360: refused before
+    # any lattice is built
+    with pytest.raises(ValueError):
+        pool_refinement((160, 240, 360), steps0=1000, every0=100, tau0=500, m0=200,
+                        shift_every0=100)
+    with pytest.raises(ValueError):
+        pool_refinement((160, 240), steps0=640, every0=64, tau0=512, m0=256, shift_every0=64)
