@@ -18,6 +18,10 @@ Step n -> n+1 (Sec. 2), in this order:
      and at wall nodes Eq. shanchen-walls with F^ads of
      Eq. psi-based-formula); F = F^m + g (rho - rho_bar) e_y;
      Q = kappa G/2 psi sum_i W_i (psi_nb(i) - psi) c_i c_i     Eqs. Q, Q-psi-based
+     With the modified-psi model the solid neighbours of F^m carry
+     (G_w / G) psi(x), which gives F^ads = -G_w psi^2 sum W_i s c_i
+     (Eq. mod-psi-based-formula), and those of Q carry psi(x), so that
+     they drop out (Eq. Q-mod-psi-based).
   5. u = (j + F/2) / rho                            Eq. DensityAndVelocityRelationToF
   6. m = M f;  m* = m - Lambda (m - m_eq) + (I - Lambda/2) S + C;
      f* = M^-1 m*                                   Eqs. collisionMRT, li_source_terms, S, C
@@ -81,6 +85,7 @@ from . import lattice as lat
 from .thermo import EOS
 
 FREE, DIRICHLET, ADIABATIC = 0, 1, 2
+PSI_BASED, MODIFIED_PSI = 0, 1  # contact-angle models of Sec. 2.2
 NEWTON_WALL = 8  # Newton steps of the wall-density equation (fixed count)
 
 
@@ -111,8 +116,14 @@ class Params:
     rho_v: float = 0.38
     gy: float = 0.0  # gravity along y (negative = downwards)
     walls: bool = False  # Zou-He walls at y = 0 and y = ny-1
+    # contact-angle model of the walls (Sec. 2.2): PSI_BASED uses the wall
+    # densities rho_w (Eq. psi-based-formula), MODIFIED_PSI the adhesion
+    # strengths G_w (Eq. mod-psi-based-formula); per column
+    wall_model: int = 0
     rho_w_bottom: np.ndarray = None  # [nx] psi-based wall densities
     rho_w_top: np.ndarray = None
+    gw_bottom: np.ndarray = None  # [nx] modified-psi adhesion strengths
+    gw_top: np.ndarray = None
     thermal: bool = False
     n_iso: int = 0  # first n_iso steps keep T frozen
     cv: float = 5.0
@@ -137,6 +148,10 @@ class Params:
             return np.full(nx, v, dtype=dt) if v.ndim == 0 else v.copy()
         self.rho_w_bottom = col(self.rho_w_bottom, 1.0)
         self.rho_w_top = col(self.rho_w_top, 1.0)
+        self.gw_bottom = col(self.gw_bottom, self.G)
+        self.gw_top = col(self.gw_top, self.G)
+        if self.wall_model not in (PSI_BASED, MODIFIED_PSI):
+            raise ValueError("wall_model must be PSI_BASED or MODIFIED_PSI")
         self.t_bottom_kind = col(self.t_bottom_kind, FREE, np.int64)
         self.t_top_kind = col(self.t_top_kind, FREE, np.int64)
         self.t_bottom_val = col(self.t_bottom_val, 0.0)
@@ -227,7 +242,8 @@ class Sim:
         return psi, psi_w_bot, psi_w_top
 
     def neighbour_psi(self, psi, psi_w_bot, psi_w_top):
-        """psi_nb[i][y, x] = psi(x + c_i), or psi_w(x) if x + c_i is solid."""
+        """psi_nb[i][y, x] = psi(x + c_i), or the given solid value at x
+        (one per column and wall) if x + c_i is solid."""
         ny = self.p.ny
         nb = []
         for i in range(9):
@@ -240,7 +256,12 @@ class Sim:
             nb.append(v)
         return nb
 
-    def forces(self, rho, psi, nb, rho_bar):
+    def forces(self, rho, psi, nb, nbq, rho_bar):
+        """nb: neighbour psi seen by F^m (solid neighbours carry psi_w, or
+        (G_w / G) psi(x) for the modified model, which turns G psi psi_nb
+        into the G_w psi^2 of Eq. mod-psi-based-formula); nbq: neighbour psi
+        seen by Q (Eq. Q-psi-based, or psi(x) itself for solid neighbours
+        under Eq. Q-mod-psi-based)."""
         G = self.p.G
         sx = sum(lat.W_INT[i] * nb[i] * lat.CX[i] for i in range(1, 9))
         sy = sum(lat.W_INT[i] * nb[i] * lat.CY[i] for i in range(1, 9))
@@ -249,7 +270,7 @@ class Sim:
         fx = fmx
         fy = fmy + self.p.gy * (rho - rho_bar)
         k = self.p.kappa * G / 2.0 * psi
-        d = [nb[i] - psi for i in range(9)]
+        d = [nbq[i] - psi for i in range(9)]
         qxx = k * sum(lat.W_INT[i] * d[i] * lat.CX[i] * lat.CX[i] for i in range(1, 9))
         qyy = k * sum(lat.W_INT[i] * d[i] * lat.CY[i] * lat.CY[i] for i in range(1, 9))
         qxy = k * sum(lat.W_INT[i] * d[i] * lat.CX[i] * lat.CY[i] for i in range(1, 9))
@@ -351,17 +372,30 @@ class Sim:
             else:
                 K = fr[0] + fr[1] + fr[3] + 2.0 * (fr[2] + fr[5] + fr[6])
             pa = psi_int[adj - 1]
-            pw = eos.psi(rw, T[row])
-            # F^m_y = psi(rho) * B: fluid neighbours in the adjacent row
-            # (weights 1/3, 1/12, 1/12, c_y = sgn), solid ones psi_w (c_y = -sgn)
+            # F^m_y: fluid neighbours in the adjacent row (weights 1/3,
+            # 1/12, 1/12, c_y = sgn), solid ones (c_y = -sgn, weights summing
+            # to 1/2)
             nbsum = pa / 3.0 + (np.roll(pa, -1) + np.roll(pa, 1)) / 12.0
-            B = -G * sgn * (nbsum - 0.5 * pw)
-            # bottom: rho + psi(rho) B / 2 = K ; top: rho - psi(rho) B / 2 = K
             r = K.copy()
-            for _ in range(NEWTON_WALL):
-                g = r + sgn * 0.5 * eos.psi(r, T[row]) * B - K
-                dg = 1.0 + sgn * 0.5 * eos.dpsi_drho(r, T[row]) * B
-                r = r - g / dg
+            if p.wall_model == PSI_BASED:
+                # F^m_y = psi(rho) B with psi_w for the solid neighbours;
+                # bottom: rho + psi(rho) B / 2 = K ; top: rho - psi(rho) B / 2 = K
+                pw = eos.psi(rw, T[row])
+                B = -G * sgn * (nbsum - 0.5 * pw)
+                for _ in range(NEWTON_WALL):
+                    g = r + sgn * 0.5 * eos.psi(r, T[row]) * B - K
+                    dg = 1.0 + sgn * 0.5 * eos.dpsi_drho(r, T[row]) * B
+                    r = r - g / dg
+            else:
+                # Eq. mod-psi-based-formula: F^m_y = sgn (-G psi nbsum +
+                # G_w psi^2 / 2), so rho + (-G psi nbsum + G_w psi^2 / 2) / 2 = K
+                gw = p.gw_bottom if sgn > 0 else p.gw_top
+                for _ in range(NEWTON_WALL):
+                    ps = eos.psi(r, T[row])
+                    dps = eos.dpsi_drho(r, T[row])
+                    g = r + 0.5 * (-G * ps * nbsum + 0.5 * gw * ps * ps) - K
+                    dg = 1.0 + 0.5 * (-G * nbsum + gw * ps) * dps
+                    r = r - g / dg
             out.append(r)
         return out[0], out[1]
 
@@ -394,8 +428,13 @@ class Sim:
             rho[0, :], rho[p.ny - 1, :] = rb, rt
         rho_bar = rho.mean() if p.gy != 0.0 else 0.0
         psi, pwb, pwt = self.psi_fields(rho, T)
-        nb = self.neighbour_psi(psi, pwb, pwt)
-        fmx, fmy, fx, fy, qxx, qyy, qxy = self.forces(rho, psi, nb, rho_bar)
+        if p.walls and p.wall_model == MODIFIED_PSI:
+            ny = p.ny
+            nb = self.neighbour_psi(psi, p.gw_bottom / p.G * psi[0], p.gw_top / p.G * psi[ny - 1])
+            nbq = self.neighbour_psi(psi, psi[0], psi[ny - 1])
+        else:
+            nb = nbq = self.neighbour_psi(psi, pwb, pwt)
+        fmx, fmy, fx, fy, qxx, qyy, qxy = self.forces(rho, psi, nb, nbq, rho_bar)
         if p.walls:
             ny = p.ny
             self.close_populations(f, -0.5 * fmx[0], -0.5 * fmy[0],
