@@ -55,6 +55,8 @@ typedef enum {
 
 enum { LBM_FP64 = 0, LBM_FP32_SHIFTED = 1 };          /* storage precision */
 enum { LBM_T_FREE = 0, LBM_T_DIRICHLET = 1, LBM_T_ADIABATIC = 2 };
+/* contact-angle model of the walls (Sec. 2.2) */
+enum { LBM_WALL_PSI_BASED = 0, LBM_WALL_MODIFIED_PSI = 1 };
 
 /* All quantities in lattice units.  lbm_default_params() fills the values
  * used by the paper's droplet runs (Sec. 4.1) on the ladder EOS a = 2/49. */
@@ -81,7 +83,13 @@ typedef struct lbm_params {
   int32_t xcd_remap;             /* 1: keep neighbouring tiles on one XCD */
   int32_t strip_waves;           /* waves per strip of the energy step: 1, 2, or 0 = by lattice
                                     size (2 on lattices with fewer than 2048 five-row strips) */
-  int32_t reserved_i[6];
+  int32_t wall_model;            /* LBM_WALL_PSI_BASED: adhesion of Eq. psi-based-formula with
+                                    the per-column wall densities rho_w, Q of Eq. Q-psi-based;
+                                    LBM_WALL_MODIFIED_PSI: adhesion of Eq. mod-psi-based-formula
+                                    with per-column strengths G_w, Q of Eq. Q-mod-psi-based.
+                                    Either way the Zou-He closure imposes zero fluid velocity
+                                    with the chosen F^m (wall density from a Newton solve) */
+  int32_t reserved_i[5];
   double reserved_d[8];
 } lbm_params;
 

@@ -136,10 +136,15 @@ __device__ __forceinline__ void wall_mass_body(const WallArgs<S>& A, const int b
       const double Ta = double(C(A.Tin[ra + xs[j]]));
       pa[j] = psi_fast(rho, Ta, eos_node(rho, Ta, A.ph), A.ph, err);
     }
-    const double rw = bot ? A.tab.rho_w_b[x] : A.tab.rho_w_t[x];
-    const double psiw = psi_checked(rw, Tw, A.ph, err);
-    const double B = wall_coef_B(pa[0], pa[1], pa[2], psiw, sgn, A.ph);
-    dm = wall_density(K, B, Tw, sgn, A.ph) - K;
+    const double rw = bot ? A.tab.rho_w_b[x] : A.tab.rho_w_t[x];  // rho_w, or G_w (modified-psi)
+    if (A.ph.wall_mod) {
+      const double nbsum = pa[0] / 3.0 + (pa[1] + pa[2]) / 12.0;
+      dm = wall_density_mod(K, nbsum, rw, Tw, A.ph) - K;
+    } else {
+      const double psiw = psi_checked(rw, Tw, A.ph, err);
+      const double B = wall_coef_B(pa[0], pa[1], pa[2], psiw, sgn, A.ph);
+      dm = wall_density(K, B, Tw, sgn, A.ph) - K;
+    }
   }
   __shared__ double red[256 / kLanes];
   const double ws = wave_sum(dm);

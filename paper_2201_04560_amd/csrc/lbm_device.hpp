@@ -33,6 +33,7 @@ struct Phys {
   double cv, lambda_l, lambda_v, dlam;  // dlam = (lambda_l - lambda_v)/(rho_l - rho_v)
   double t_side_val;
   double rho_ref;
+  int wall_mod;  // 1: modified-psi walls (the wall tables hold G_w)
 };
 
 // constants of the collision and the energy update in the compute type C
@@ -174,6 +175,24 @@ __device__ __forceinline__ double wall_density(double K, double B, double T, dou
     const double ps = sqrt(psi_radicand(r, T, p));
     const double g = r + sgn * 0.5 * ps * B - K;
     const double dg = 1.0 + sgn * 0.5 * dpsi_drho(r, T, ps, p) * B;
+    r = r - g / dg;
+  }
+  return r;
+}
+
+// Modified-psi walls (Eq. mod-psi-based-formula): F^m_y = sgn (-G psi nbsum
+// + G_w psi^2 / 2) with nbsum the fluid neighbours' weighted psi, so zero
+// fluid velocity asks rho + (-G psi nbsum + G_w psi^2 / 2) / 2 = K at both
+// walls; Newton from rho = K
+__device__ __forceinline__ double wall_density_mod(double K, double nbsum, double gw, double T,
+                                                   const Phys& p) {
+  double r = K;
+#pragma unroll 1
+  for (int it = 0; it < kNewtonWall; ++it) {
+    const double ps = sqrt(psi_radicand(r, T, p));
+    const double dps = dpsi_drho(r, T, ps, p);
+    const double g = r + 0.5 * (-p.G * ps * nbsum + 0.5 * gw * ps * ps) - K;
+    const double dg = 1.0 + 0.5 * (-p.G * nbsum + gw * ps) * dps;
     r = r - g / dg;
   }
   return r;

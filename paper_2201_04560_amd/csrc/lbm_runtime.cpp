@@ -119,6 +119,7 @@ Phys make_phys(const lbm_params& p) {
   h.dlam = (p.lambda_l - p.lambda_v) / (p.rho_l - p.rho_v);
   h.t_side_val = p.t_side_val;
   h.rho_ref = p.precision == LBM_FP32_SHIFTED ? p.rho_ref : 0.0;
+  h.wall_mod = p.wall_model == LBM_WALL_MODIFIED_PSI ? 1 : 0;
   return h;
 }
 
@@ -194,6 +195,8 @@ lbm_status lbm_validate(const lbm_params* p) {
   if (p->tile_y < 0 || p->tile_y == 1) return bad("tile_y must be 0 or >= 2");
   if (p->strip_waves < 0 || p->strip_waves > 2) return bad("strip_waves must be 0, 1 or 2");
   if (!std::isfinite(p->rho_ref)) return bad("rho_ref must be finite");
+  if (p->wall_model != LBM_WALL_PSI_BASED && p->wall_model != LBM_WALL_MODIFIED_PSI)
+    return bad("wall_model must be LBM_WALL_PSI_BASED or LBM_WALL_MODIFIED_PSI");
   return LBM_OK;
 }
 
@@ -229,8 +232,9 @@ lbm_status lbm_create(const lbm_params* p, void* dev_buf, size_t bytes, void* hi
   c->base = static_cast<char*>(dev_buf);
   c->bytes = bytes;
   const int nx = p->nx;
-  c->rw_b.assign(nx, 1.0);
-  c->rw_t.assign(nx, 1.0);
+  // psi-based: rho_w = 1; modified-psi: G_w = G (a neutral wall)
+  c->rw_b.assign(nx, p->wall_model == LBM_WALL_MODIFIED_PSI ? p->G : 1.0);
+  c->rw_t.assign(nx, p->wall_model == LBM_WALL_MODIFIED_PSI ? p->G : 1.0);
   c->tv_b.assign(nx, 0.0);
   c->tv_t.assign(nx, 0.0);
   c->tk_b.assign(nx, LBM_T_FREE);
@@ -297,6 +301,10 @@ lbm_status lbm_set_boundary(lbm_ctx* c, const double* rho_w_bottom, const double
           (t_top_kind && t_top_kind[i] == LBM_T_ADIABATIC))
         return fail(c, LBM_E_INVAL, "ADIABATIC rows need ny >= 3");
   }
+  for (const double* w : {rho_w_bottom, rho_w_top})
+    if (w)
+      for (int i = 0; i < nx; ++i)
+        if (!std::isfinite(w[i])) return fail(c, LBM_E_INVAL, "wall tables must be finite");
   if (rho_w_bottom) c->rw_b.assign(rho_w_bottom, rho_w_bottom + nx);
   if (rho_w_top) c->rw_t.assign(rho_w_top, rho_w_top + nx);
   if (t_bottom_kind) c->tk_b.assign(t_bottom_kind, t_bottom_kind + nx);

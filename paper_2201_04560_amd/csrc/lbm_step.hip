@@ -346,13 +346,23 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
     const double sgn = bottom ? 1.0 : -1.0;
     const double K = s_rho[SW][lane];
     const double Tw = double(s_T[SW][lane]);
-    const double rw = A.tabd[(bottom ? 0 : 1) * nx + x];
-    const double psiw = psi_checked(rw, Tw, P, err);
-    const double B = wall_coef_B(s_psi[SN][lane], s_psi[SN][lp], s_psi[SN][lm], psiw, sgn, P);
-    const double rwall = wall_density(K, B, Tw, sgn, P);
+    const double rw = A.tabd[(bottom ? 0 : 1) * nx + x];  // rho_w, or G_w (modified-psi)
+    double psiw, rwall, psiwall;
+    if (P.wall_mod) {
+      const double nbsum = s_psi[SN][lane] / 3.0 + (s_psi[SN][lp] + s_psi[SN][lm]) / 12.0;
+      rwall = wall_density_mod(K, nbsum, rw, Tw, P);
+      psiwall = psi_checked(rwall, Tw, P, err);
+      // solid neighbours seen by F^m: G psi psi_s = G_w psi^2
+      psiw = rw / P.G * psiwall;
+    } else {
+      psiw = psi_checked(rw, Tw, P, err);
+      const double B = wall_coef_B(s_psi[SN][lane], s_psi[SN][lp], s_psi[SN][lm], psiw, sgn, P);
+      rwall = wall_density(K, B, Tw, sgn, P);
+      psiwall = psi_checked(rwall, Tw, P, err);
+    }
     s_rho[SW][lane] = rwall;
     if constexpr (kRhoC) s_rc[SW][lane] = C(rwall);
-    s_psi[SW][lane] = psi_checked(rwall, Tw, P, err);
+    s_psi[SW][lane] = psiwall;
     if (bottom) psiw_b = psiw; else psiw_t = psiw;
   };
 
@@ -467,8 +477,13 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
     const double rho = s_rho[kc][lane];
     const double G = P.G;
     // Eq. shanchen (psi_w for solid neighbours: Eq. shanchen-walls)
-    const double d1 = p1 - pc, d2 = p2 - pc, d3 = p3 - pc, d4 = p4 - pc;
-    const double d5 = p5 - pc, d6 = p6 - pc, d7 = p7 - pc, d8 = p8 - pc;
+    double d1 = p1 - pc, d2 = p2 - pc, d3 = p3 - pc, d4 = p4 - pc;
+    double d5 = p5 - pc, d6 = p6 - pc, d7 = p7 - pc, d8 = p8 - pc;
+    if (WALLS && P.wall_mod) {
+      // Eq. Q-mod-psi-based: solid neighbours drop out of Q
+      if (wb) d4 = d7 = d8 = 0.0;
+      if (wt) d2 = d5 = d6 = 0.0;
+    }
     const double sx = (1.0 / 3.0) * (p1 - p3) + (1.0 / 12.0) * ((p5 - p7) + (p8 - p6));
     const double sy = (1.0 / 3.0) * (p2 - p4) + (1.0 / 12.0) * ((p5 - p7) + (p6 - p8));
     const double fmx = -G * pc * sx;

@@ -72,8 +72,17 @@ class Lattice:
 
     # ------------------------------------------------------------------ API
     def set_boundary(self, rho_w_bottom=None, rho_w_top=None, t_bottom_kind=None, t_bottom_val=None,
-                     t_top_kind=None, t_top_val=None):
+                     t_top_kind=None, t_top_val=None, gw_bottom=None, gw_top=None):
+        """Per-column wall tables: rho_w (psi-based walls) or G_w
+        (modified-psi walls, wall_model = 1), and temperature kinds and
+        values of the two wall rows; None keeps the current values."""
         nx = self.nx
+        if gw_bottom is not None or gw_top is not None:
+            if self.p.wall_model != 1:
+                raise ValueError("G_w needs wall_model = 1 (modified-psi walls)")
+            if rho_w_bottom is not None or rho_w_top is not None:
+                raise ValueError("give rho_w or G_w, not both")
+            rho_w_bottom, rho_w_top = gw_bottom, gw_top
 
         def col(v, dt):
             if v is None:

@@ -14,7 +14,7 @@ def oracle_params(c):
     keys = ["nx", "ny", "a", "sigma", "kappa", "s_rho", "s_e", "s_zeta", "s_j", "s_q", "eta_l",
             "eta_v", "rho_l", "rho_v", "gy", "walls", "thermal", "n_iso", "cv", "lambda_l",
             "lambda_v", "rho_w_bottom", "rho_w_top", "t_bottom_kind", "t_bottom_val", "t_top_kind",
-            "t_top_val", "t_side_dirichlet", "t_side_val"]
+            "t_top_val", "t_side_dirichlet", "t_side_val", "wall_model", "gw_bottom", "gw_top"]
     return Params(**{k: c[k] for k in keys if k in c})
 
 
@@ -24,7 +24,7 @@ def lib_params(c, precision=0, tile_y=0, rho_ref=None, xcd_remap=1, strip_waves=
     scal = ["a", "sigma", "kappa", "s_rho", "s_e", "s_zeta", "s_j", "s_q", "eta_l", "eta_v",
             "rho_l", "rho_v", "gy", "cv", "lambda_l", "lambda_v", "t_side_val"]
     kw = {k: float(c[k]) for k in scal if k in c}
-    for k in ("walls", "thermal", "n_iso", "t_side_dirichlet"):
+    for k in ("walls", "thermal", "n_iso", "t_side_dirichlet", "wall_model"):
         if k in c:
             kw[k] = int(c[k])
     kw["precision"] = precision
@@ -38,7 +38,10 @@ def lib_params(c, precision=0, tile_y=0, rho_ref=None, xcd_remap=1, strip_waves=
 def lib_boundary(lat, c):
     nx = c["nx"]
     col = lambda k, d: np.broadcast_to(np.asarray(c.get(k, d)), (nx,))
-    lat.set_boundary(col("rho_w_bottom", 1.0), col("rho_w_top", 1.0),
+    # the wall tables hold rho_w (psi-based) or G_w (modified-psi walls)
+    wb, wt = ("gw_bottom", "gw_top") if c.get("wall_model", 0) == 1 else ("rho_w_bottom", "rho_w_top")
+    dflt = -1.0 if c.get("wall_model", 0) == 1 else 1.0
+    lat.set_boundary(col(wb, dflt), col(wt, dflt),
                      col("t_bottom_kind", 0).astype(np.int32), col("t_bottom_val", 0.0),
                      col("t_top_kind", 0).astype(np.int32), col("t_top_val", 0.0))
 
@@ -59,9 +62,10 @@ def droplet128():
     return c, rho, Tf
 
 
-def random_tiny(nx, ny, seed, walls=False, thermal=False, gy=0.0):
+def random_tiny(nx, ny, seed, walls=False, thermal=False, gy=0.0, wall_model=0):
     """Random near-equilibrium state inside the EOS domain, exercising every
-    term: walls with random wall densities, mixed temperature kinds."""
+    term: walls with random wall densities (or random G_w for modified-psi
+    walls), mixed temperature kinds."""
     eos, T, rv, rl = coexistence()
     rng = np.random.default_rng(seed)
     c = dict(nx=nx, ny=ny, a=2.0 / 49.0, sigma=0.11, kappa=0.3, rho_l=rl, rho_v=rv,
@@ -70,6 +74,10 @@ def random_tiny(nx, ny, seed, walls=False, thermal=False, gy=0.0):
     if walls:
         c["rho_w_bottom"] = rng.uniform(0.5, 6.0, nx)
         c["rho_w_top"] = rng.uniform(0.5, 6.0, nx)
+        if wall_model == 1:
+            c["wall_model"] = 1
+            c["gw_bottom"] = rng.uniform(-1.4, -0.6, nx)
+            c["gw_top"] = rng.uniform(-1.4, -0.6, nx)
         kb = rng.integers(1, 3, nx)
         kt = rng.integers(1, 3, nx)
         c["t_bottom_kind"], c["t_top_kind"] = kb, kt

@@ -55,7 +55,8 @@ def test_validation(lib):
     assert lib.lbm_validate(ctypes.byref(ok)) == LBM_OK
     bad = [dict(nx=0), dict(ny=0), dict(a=0.0), dict(b=-1.0), dict(s_e=2.0), dict(s_q=0.0),
            dict(precision=7), dict(walls=1, ny=2), dict(thermal=1, cv=0.0), dict(tile_y=1),
-           dict(rho_l=1.0, rho_v=1.0), dict(G=1.0), dict(n_iso=-1)]
+           dict(rho_l=1.0, rho_v=1.0), dict(G=1.0), dict(n_iso=-1), dict(wall_model=2),
+           dict(wall_model=-1), dict(strip_waves=3)]
     for kw in bad:
         nx = kw.pop("nx", 16)
         ny = kw.pop("ny", 16)
