@@ -468,6 +468,10 @@ def main():
     ap.add_argument("--pool-refinement-study", action="store_true",
                     help="also run the Sec. 4.3 pool refinement (meshes 160..540, 40000 base "
                          "steps, rho_wh 0.38, T_h 1.2 T_c, float64, about 40 s of GPU time)")
+    ap.add_argument("--contact-angle-study", action="store_true",
+                    help="also run the Sec. 4.3 contact-angle tests: the G_w search of the "
+                         "modified-psi model (meshes 160..540) and the psi-based refinement "
+                         "(meshes 160..810), float64, about 130 s of GPU time")
     ap.add_argument("--pool-steps", type=int, default=5000,
                     help="steps of the 1024 x 2048 pool in the float32 accuracy check")
     ap.add_argument("--tile-cache", default=None, help="JSON cache of autotuned strip heights")
@@ -615,6 +619,16 @@ def main():
             ps[k] = np.round(np.asarray(ps[k])[:, ::8], 5).tolist()
         ps["wall_s"] = round(time.perf_counter() - t0, 1)
         out["pool_refinement_study"] = ps
+    if args.contact_angle_study:
+        from paper_2201_04560_amd.ladder import contact_angle_refinement, gw_search
+
+        log("bench: contact-angle study (G_w search 160..540, psi-based refinement 160..810)")
+        t0 = time.perf_counter()
+        cs = {"gw_search": gw_search(progress=lambda k, n: log(f"bench:   G_w mesh {k}/{n}")),
+              "psi_based": contact_angle_refinement(
+                  progress=lambda k, n: log(f"bench:   psi-based check {k}/{n}"))}
+        cs["wall_s"] = round(time.perf_counter() - t0, 1)
+        out["contact_angle_study"] = cs
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(case)

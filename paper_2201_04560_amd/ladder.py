@@ -419,3 +419,181 @@ def pool_refinement(meshes=(160, 240, 360, 540), N0=160, steps0=40000, every0=64
         out[f"D_shifted_{name}"] = Ds
         out[f"orders_shifted_{name}"] = orders(Ds)
     return out
+
+
+def contact_angle(rho, rho_l, rho_v, ymin=3.0, y_wall=0.0):
+    """Static contact angle (degrees) of a droplet on the bottom wall: a
+    circle fitted by algebraic least squares to the crossings of
+    rho = (rho_l + rho_v) / 2 along rows and columns (linear interpolation)
+    at heights y >= ymin, and the angle it makes with the wall plane
+    y = y_wall inside the liquid, cos(theta) = (y_wall - y_c) / R."""
+    import numpy as np
+
+    mid = 0.5 * (rho_l + rho_v)
+    ny, nx = rho.shape
+    y0 = int(np.ceil(ymin))
+    a = rho[y0:] - mid
+    pts = []
+    # crossings along columns (between rows y and y + 1) and rows
+    s = a[:-1] * a[1:] < 0
+    yy, xx = np.nonzero(s)
+    t = a[yy, xx] / (a[yy, xx] - a[yy + 1, xx])
+    pts.append(np.c_[xx, y0 + yy + t])
+    s = a[:, :-1] * a[:, 1:] < 0
+    yy, xx = np.nonzero(s)
+    t = a[yy, xx] / (a[yy, xx] - a[yy, xx + 1])
+    pts.append(np.c_[xx + t, y0 + yy])
+    P = np.concatenate(pts).astype(float)
+    if len(P) < 8:
+        raise ValueError("no droplet interface above ymin")
+    M = np.c_[2.0 * P, np.ones(len(P))]
+    (xc, yc, c), *_ = np.linalg.lstsq(M, (P ** 2).sum(1), rcond=None)
+    R = float(np.sqrt(c + xc * xc + yc * yc))
+    return float(np.degrees(np.arccos(np.clip((y_wall - yc) / R, -1.0, 1.0))))
+
+
+def wall_droplet_mesh(N, value, model=0, N0=160, a0=6.12e-2, Tr=0.86, R0_frac=0.25, eta=0.1,
+                      precision=0, tile_y=0):
+    """Mesh N (N x N) of the contact-angle tests of Sec. 4.3: periodic sides,
+    Zou-He walls, isothermal at T_sat = Tr T_c, no gravity; a half disk of
+    liquid of radius R0_frac N centred on the bottom wall (smoothed over one
+    base-mesh node); bottom wall table = value (rho_w for the psi-based
+    model 0, G_w for the modified-psi model 1), top wall rho_w = rho_v or
+    G_w = G; a, sigma, kappa by the refinement rules with dx = N0 / N.
+    Returns (params, boundary, rho, T, level record)."""
+    import numpy as np
+
+    from .sim import make_params, refinement_level
+
+    dx = N0 / N
+    lv = refinement_level(a0, dx, Tr, 0.0, 0.0)
+    rates = dict(s_rho=1.0, s_e=0.8, s_zeta=0.8, s_j=1.0, s_q=1.1)
+    p = make_params(N, N, a=lv["a"], sigma=lv["sigma"], kappa=lv["kappa"], rho_l=lv["rho_l"],
+                    rho_v=lv["rho_v"], walls=1, thermal=0, gy=0.0, eta_l=eta, eta_v=eta,
+                    rho_ref=lv["rho_v"], wall_model=int(model), precision=precision, tile_y=tile_y,
+                    **rates)
+    top = lv["rho_v"] if model == 0 else p.G
+    bnd = dict(rho_w_bottom=np.full(N, float(value)), rho_w_top=np.full(N, top),
+               t_bottom_kind=np.full(N, 1, np.int32), t_bottom_val=lv["T"],
+               t_top_kind=np.full(N, 1, np.int32), t_top_val=lv["T"])
+    y, x = np.mgrid[0:N, 0:N] + 0.5
+    d = np.hypot(x - N / 2, y - 0.5)
+    rho = 0.5 * (lv["rho_l"] + lv["rho_v"]) - 0.5 * (lv["rho_l"] - lv["rho_v"]) * np.tanh(
+        (d - R0_frac * N) * dx)
+    return p, bnd, rho, np.full((N, N), lv["T"]), lv
+
+
+def wall_droplets(meshes, values, model=0, N0=160, steps0=20000, checks=(0.5, 0.75, 1.0),
+                  precision=0, progress=None, keep_fields=False, **kw):
+    """Every (mesh, value) droplet of wall_droplet_mesh in one batch, run for
+    steps0 base-mesh steps ((N / N0)^2 steps on mesh N).  Returns the
+    contact angles at the fractions `checks` of the run (the last one is the
+    static angle; the others show whether it has settled) and, with
+    keep_fields, the final densities."""
+    import numpy as np
+
+    from .sim import Batch, Lattice
+
+    lats, levels, keys = [], [], []
+    for N in meshes:
+        for v in values:
+            p, bnd, rho, T, lv = wall_droplet_mesh(N, v, model, N0, precision=precision, **kw)
+            lat = Lattice(p)
+            lat.set_boundary(**bnd)
+            lat.init_fields(rho, None, None, T)
+            lats.append(lat)
+            levels.append(lv)
+            keys.append((N, v))
+    b = Batch(lats)
+    angles = np.zeros((len(checks), len(meshes), len(values)))
+    fields = {}
+    done = [0] * len(lats)
+    for k, frac in enumerate(checks):
+        target = [int(round(frac * steps0 * (N / N0) ** 2)) for N, _ in keys]
+        b.run([t - d for t, d in zip(target, done)])
+        done = target
+        for j, (lat, lv, (N, v)) in enumerate(zip(lats, levels, keys)):
+            r = lat.fields()[0]
+            angles[k, j // len(values), j % len(values)] = contact_angle(
+                r, lv["rho_l"], lv["rho_v"], ymin=3.0 * N / N0)
+            if keep_fields and k == len(checks) - 1:
+                fields[(N, v)] = r
+        if progress:
+            progress(k + 1, len(checks))
+    b.close()
+    for lat in lats:
+        lat.close()
+    out = {"meshes": list(meshes), "values": list(values), "model": int(model), "steps0": steps0,
+           "checks": list(checks), "angles": angles.tolist()}
+    if keep_fields:
+        out["fields"] = fields
+    return out
+
+
+def contact_angle_refinement(meshes=(160, 240, 360, 540, 810), rho_w=(4.0, 2.3, 1.7), N0=160,
+                             steps0=20000, precision=0, progress=None, **kw):
+    """Refinement of the psi-based contact-angle droplets (Sec. 4.3): the
+    relative change of the static density fields between consecutive
+    meshes, sum |I(rho_N) - rho_N*| / sum |rho_N*| with the bilinear
+    interpolation I, its convergence orders, and the static angles."""
+    import math
+
+    import numpy as np
+
+    r = wall_droplets(meshes, rho_w, 0, N0, steps0, precision=precision, progress=progress,
+                      keep_fields=True, **kw)
+    F = r.pop("fields")
+    ratio = meshes[1] / meshes[0]
+    rel, orders = [], []
+    for v in rho_w:
+        d = [space_difference(F[(meshes[m], v)], F[(meshes[m + 1], v)]) for m in range(len(meshes) - 1)]
+        rel.append(d)
+        orders.append([math.log(d[m] / d[m + 1]) / math.log(ratio) for m in range(len(d) - 1)])
+    r["rel_change"] = rel
+    r["orders"] = orders
+    return r
+
+
+def gw_search(meshes=(160, 240, 360, 540), target=125.9, N0=160, steps0=20000,
+              coarse=(-1.0, -0.95, -0.9, -0.85, -0.8, -0.75, -0.7), fine=11, precision=0,
+              progress=None, **kw):
+    """G_w of the modified-psi model giving the static contact angle
+    `target` on each mesh (Sec. 4.3): a linear search over the coarse grid
+    (every mesh and value in one batch), then a finer grid of `fine` values
+    across the bracketing interval of each mesh, and linear interpolation
+    of the angle between the two nearest values."""
+    import numpy as np
+
+    coarse = sorted(coarse)
+    r1 = wall_droplets(meshes, coarse, 1, N0, steps0, checks=(1.0,), precision=precision,
+                       progress=progress, **kw)
+    A1 = np.asarray(r1["angles"][0])
+    out = {"meshes": list(meshes), "target": target, "coarse": coarse, "coarse_angles": A1.tolist(),
+           "gw": [], "fine": [], "fine_angles": []}
+    brackets = []
+    for m in range(len(meshes)):
+        a = A1[m]
+        j = next((j for j in range(len(a) - 1) if (a[j] - target) * (a[j + 1] - target) <= 0), None)
+        brackets.append(None if j is None else (coarse[j], coarse[j + 1]))
+    for m, N in enumerate(meshes):
+        if brackets[m] is None:
+            out["gw"].append(None)
+            out["fine"].append([])
+            out["fine_angles"].append([])
+            continue
+        lo, hi = brackets[m]
+        vals = list(np.linspace(lo, hi, fine))
+        r2 = wall_droplets((N,), vals, 1, N0, steps0, checks=(1.0,), precision=precision, **kw)
+        a = np.asarray(r2["angles"][0][0])
+        j = next((j for j in range(len(a) - 1) if (a[j] - target) * (a[j + 1] - target) <= 0), None)
+        if j is None:
+            gw = None
+        else:
+            t = (target - a[j]) / (a[j + 1] - a[j]) if a[j + 1] != a[j] else 0.0
+            gw = float(vals[j] + t * (vals[j + 1] - vals[j]))
+        out["gw"].append(gw)
+        out["fine"].append([float(v) for v in vals])
+        out["fine_angles"].append(a.tolist())
+        if progress:
+            progress(m + 1, len(meshes))
+    return out

@@ -78,3 +78,32 @@ def test_pool_refinement_rejects_fractional_intervals():
                         shift_every0=100)
     with pytest.raises(ValueError):
         pool_refinement((160, 240), steps0=640, every0=64, tau0=512, m0=256, shift_every0=64)
+
+
+def test_contact_angle_of_circular_caps():
+    """Caps cut from a tanh-profiled disk by the wall plane y = 0 at known
+    angles, from hydrophilic to nearly detached."""
+    from paper_2201_04560_amd.ladder import contact_angle
+
+    n, R = 220, 40.0
+    y, x = np.mgrid[0:n, 0:n] + 0.0
+    for th in (30.0, 60.0, 90.0, 125.9, 160.0):
+        yc = -R * np.cos(np.radians(th))
+        rho = 3.44 - 3.06 * np.tanh(np.hypot(x - 110.0, y - yc) - R)
+        assert abs(contact_angle(rho, 6.5, 0.38, ymin=3.0) - th) < 0.2, th
+
+
+def test_wall_droplet_meshes_follow_the_refinement_rules():
+    from paper_2201_04560_amd.ladder import wall_droplet_mesh
+
+    for model, v in ((0, 2.3), (1, -0.9)):
+        base = wall_droplet_mesh(160, v, model)
+        for N in (160, 240, 360):
+            p, bnd, rho, T, lv = wall_droplet_mesh(N, v, model)
+            assert p.wall_model == model and p.walls == 1 and p.thermal == 0 and p.gy == 0.0
+            assert abs(p.a / base[0].a - (160 / N) ** 2) < 1e-14
+            assert np.all(bnd["rho_w_bottom"] == v)
+            assert np.all(bnd["rho_w_top"] == (lv["rho_v"] if model == 0 else -1.0))
+            # half disk of radius N/4 on the bottom wall
+            assert rho[0, N // 2] > lv["rho_l"] - 1e-6 and rho[N // 4 + N // 8, N // 2] < lv["rho_v"] + 1e-3
+            assert abs(rho[:, :N // 2].sum() - rho[:, N // 2:][:, ::-1].sum()) < 1e-9 * rho.sum()
