@@ -126,11 +126,15 @@ lbm_status lbm_create(const lbm_params* p, void* dev_buf, size_t bytes, void* hi
 void lbm_destroy(lbm_ctx* ctx);
 
 /* Per-column boundary tables, host arrays of nx entries; NULL keeps the
- * current table (defaults: rho_w = 1, T kinds FREE, values 0).
- * rho_w_*: psi-based wall densities rho_w(x) of Eq. psi-based-formula for
- * rows 0 and ny-1; t_*_kind / t_*_val: temperature condition of rows 0 and
- * ny-1 (FREE, DIRICHLET value, or ADIABATIC = copy of the adjacent row after
- * each RK stage).  Must precede lbm_init_fields() to take effect at init. */
+ * current table (defaults: rho_w = 1 or G_w = G, T kinds FREE, values 0).
+ * rho_w_*: the wall tables of rows 0 and ny-1: with LBM_WALL_PSI_BASED the
+ * wall densities rho_w(x) of Eq. psi-based-formula (inside the EOS domain,
+ * else the next step reports LBM_E_DOMAIN), with LBM_WALL_MODIFIED_PSI the
+ * adhesion strengths G_w(x) of Eq. mod-psi-based-formula; non-finite
+ * entries are rejected with LBM_E_INVAL.  t_*_kind / t_*_val: temperature
+ * condition of rows 0 and ny-1 (FREE, DIRICHLET value, or ADIABATIC = copy
+ * of the adjacent row after each RK stage).  Must precede lbm_init_fields()
+ * to take effect at init. */
 lbm_status lbm_set_boundary(lbm_ctx* ctx, const double* rho_w_bottom, const double* rho_w_top,
                             const int32_t* t_bottom_kind, const double* t_bottom_val,
                             const int32_t* t_top_kind, const double* t_top_val);
