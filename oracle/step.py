@@ -38,6 +38,11 @@ Step n -> n+1 (Sec. 2), in this order:
      scalar equation per node (F^m_y depends on the node's own psi and on
      the adjacent interior row only) solved by NEWTON_WALL Newton steps
      from rho = K; the tangential component only splits the unknowns.
+     With outflow_top the top row is no wall but a zero-gradient outflow
+     (the 1-D boiling problem of Sec. 4.2): after streaming (and at init)
+     its populations with c_y < 0 are copied from the row below, psi above
+     it is its own (column by column), and it is updated like an interior
+     node; its temperature kind is ADIABATIC.
 
 Readings where the paper is silent or garbled (all used identically by
 the GPU library):
@@ -124,6 +129,10 @@ class Params:
     rho_w_top: np.ndarray = None
     gw_bottom: np.ndarray = None  # [nx] modified-psi adhesion strengths
     gw_top: np.ndarray = None
+    # the top row is a zero-gradient outflow (Sec. 4.2, after Lou et al.)
+    # instead of a Zou-He wall: its populations entering from above are
+    # those of the row below, and psi above it is its own
+    outflow_top: bool = False
     thermal: bool = False
     n_iso: int = 0  # first n_iso steps keep T frozen
     cv: float = 5.0
@@ -152,6 +161,8 @@ class Params:
         self.gw_top = col(self.gw_top, self.G)
         if self.wall_model not in (PSI_BASED, MODIFIED_PSI):
             raise ValueError("wall_model must be PSI_BASED or MODIFIED_PSI")
+        if self.outflow_top and not self.walls:
+            raise ValueError("outflow_top needs walls (a Zou-He wall at the bottom)")
         self.t_bottom_kind = col(self.t_bottom_kind, FREE, np.int64)
         self.t_top_kind = col(self.t_top_kind, FREE, np.int64)
         self.t_bottom_val = col(self.t_bottom_val, 0.0)
@@ -208,7 +219,7 @@ class Sim:
         rho = np.asarray(rho, dtype=self.dtype)
         ux = np.zeros_like(rho) if ux is None else np.asarray(ux, dtype=self.dtype)
         uy = np.zeros_like(rho) if uy is None else np.asarray(uy, dtype=self.dtype)
-        self.f = feq_weights(rho, ux, uy)
+        self.f = self.apply_outflow(feq_weights(rho, ux, uy))
         Tin = np.asarray(T, dtype=self.dtype).copy()
         if self.p.thermal:  # R8: Dirichlet values hold from the start
             d = self.tkind == DIRICHLET
@@ -252,7 +263,10 @@ class Sim:
                 if lat.CY[i] < 0:
                     v[0, :] = psi_w_bot
                 if lat.CY[i] > 0:
-                    v[ny - 1, :] = psi_w_top
+                    if self.p.outflow_top:  # zero gradient: the row above is the top row
+                        v[ny - 1, :] = np.roll(psi[ny - 1], -lat.CX[i])
+                    else:
+                        v[ny - 1, :] = psi_w_top
             nb.append(v)
         return nb
 
@@ -354,6 +368,16 @@ class Sim:
         f = np.empty_like(fstar)
         for i in range(9):
             f[i] = np.roll(fstar[i], (lat.CY[i], lat.CX[i]), axis=(0, 1))
+        return self.apply_outflow(f)
+
+    def apply_outflow(self, f):
+        """Zero-gradient outflow of the top row: the populations that would
+        enter it from above are those of the row below (in place)."""
+        if self.p.outflow_top:
+            ny = self.p.ny
+            for i in range(9):
+                if lat.CY[i] < 0:
+                    f[i, ny - 1] = f[i, ny - 2]
         return f
 
     # ------------------------------------------------------------- full step
@@ -365,7 +389,11 @@ class Sim:
         rho_int = f[:, 1:ny - 1, :].sum(axis=0)
         psi_int = eos.psi(rho_int, T[1:ny - 1, :])
         out = []
-        for row, adj, sgn, rw in ((0, 1, +1, p.rho_w_bottom), (ny - 1, ny - 2, -1, p.rho_w_top)):
+        rows = [(0, 1, +1, p.rho_w_bottom), (ny - 1, ny - 2, -1, p.rho_w_top)]
+        if p.outflow_top:
+            rows = rows[:1]
+            out = [None]  # no closure at the top: its density is the plain sum
+        for row, adj, sgn, rw in rows:
             fr = f[:, row, :]
             if sgn > 0:
                 K = fr[0] + fr[1] + fr[3] + 2.0 * (fr[4] + fr[7] + fr[8])
@@ -397,7 +425,7 @@ class Sim:
                     dg = 1.0 + 0.5 * (-G * nbsum + gw * ps) * dps
                     r = r - g / dg
             out.append(r)
-        return out[0], out[1]
+        return (out[1], out[0]) if p.outflow_top else (out[0], out[1])
 
     @staticmethod
     def close_populations(f, jxw_b, jyw_b, jxw_t, jyw_t):
@@ -425,7 +453,9 @@ class Sim:
         rho, jx, jy = self.moments(f)
         if p.walls:
             rb, rt = self.wall_closure(f, T)
-            rho[0, :], rho[p.ny - 1, :] = rb, rt
+            rho[0, :] = rb
+            if not p.outflow_top:
+                rho[p.ny - 1, :] = rt
         rho_bar = rho.mean() if p.gy != 0.0 else 0.0
         psi, pwb, pwt = self.psi_fields(rho, T)
         if p.walls and p.wall_model == MODIFIED_PSI:
@@ -437,11 +467,14 @@ class Sim:
         fmx, fmy, fx, fy, qxx, qyy, qxy = self.forces(rho, psi, nb, nbq, rho_bar)
         if p.walls:
             ny = p.ny
+            top = f[:, ny - 1].copy()
             self.close_populations(f, -0.5 * fmx[0], -0.5 * fmy[0],
                                    -0.5 * fmx[ny - 1], -0.5 * fmy[ny - 1])
-            for row in (0, ny - 1):
+            for row in ((0,) if p.outflow_top else (0, ny - 1)):
                 jx[row] = -0.5 * fmx[row]
                 jy[row] = -0.5 * fmy[row]
+            if p.outflow_top:
+                f[:, ny - 1] = top
         ux = (jx + 0.5 * fx) / rho
         uy = (jy + 0.5 * fy) / rho
         return dict(f=f, rho=rho, jx=jx, jy=jy, rho_bar=rho_bar, psi=psi, fmx=fmx, fmy=fmy,
