@@ -472,6 +472,10 @@ def main():
                     help="also run the Sec. 4.3 contact-angle tests: the G_w search of the "
                          "modified-psi model (meshes 160..540) and the psi-based refinement "
                          "(meshes 160..810), float64, about 130 s of GPU time")
+    ap.add_argument("--stefan-study", action="store_true",
+                    help="also run the Sec. 4.2 1-D boiling refinement (columns of 160..2560 "
+                         "nodes, both parameter sets, 40000 base steps, float64, about 4 min "
+                         "of GPU time)")
     ap.add_argument("--pool-steps", type=int, default=5000,
                     help="steps of the 1024 x 2048 pool in the float32 accuracy check")
     ap.add_argument("--tile-cache", default=None, help="JSON cache of autotuned strip heights")
@@ -629,6 +633,18 @@ def main():
                   progress=lambda k, n: log(f"bench:   psi-based check {k}/{n}"))}
         cs["wall_s"] = round(time.perf_counter() - t0, 1)
         out["contact_angle_study"] = cs
+    if args.stefan_study:
+        from paper_2201_04560_amd.ladder import stefan_refinement
+
+        log("bench: Stefan refinement study 160..2560")
+        t0 = time.perf_counter()
+        ss = stefan_refinement(progress=lambda k, n: log(f"bench:   sample {k}/{n}"))
+        for d in ss["sets"].values():
+            d["s"] = np.round(np.asarray(d["s"])[:, ::10], 3).tolist()
+            d["reference"] = np.round(np.asarray(d["reference"])[::10], 3).tolist()
+        ss["t"] = ss["t"][::10]
+        ss["wall_s"] = round(time.perf_counter() - t0, 1)
+        out["stefan_study"] = ss
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(case)

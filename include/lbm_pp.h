@@ -89,7 +89,13 @@ typedef struct lbm_params {
                                     with per-column strengths G_w, Q of Eq. Q-mod-psi-based.
                                     Either way the Zou-He closure imposes zero fluid velocity
                                     with the chosen F^m (wall density from a Newton solve) */
-  int32_t reserved_i[5];
+  int32_t outflow_top;           /* 1: row ny-1 is a zero-gradient outflow (the open end of the
+                                    1-D boiling problem, Sec. 4.2) instead of a wall: its
+                                    populations entering from above are those of row ny-2, psi
+                                    above it is its own, its temperature kind must be ADIABATIC
+                                    or DIRICHLET; needs walls = 1 and gy = 0
+                                    (LBM_E_UNSUPPORTED otherwise) */
+  int32_t reserved_i[4];
   double reserved_d[8];
 } lbm_params;
 

@@ -25,7 +25,7 @@ class LbmParams(ctypes.Structure):
         ("eta_l", c_double), ("eta_v", c_double), ("rho_l", c_double), ("rho_v", c_double),
         ("gy", c_double), ("cv", c_double), ("lambda_l", c_double), ("lambda_v", c_double),
         ("t_side_val", c_double), ("rho_ref", c_double),
-        ("xcd_remap", c_int32), ("strip_waves", c_int32), ("wall_model", c_int32), ("reserved_i", c_int32 * 5), ("reserved_d", c_double * 8),
+        ("xcd_remap", c_int32), ("strip_waves", c_int32), ("wall_model", c_int32), ("outflow_top", c_int32), ("reserved_i", c_int32 * 4), ("reserved_d", c_double * 8),
     ]
 
 

@@ -33,7 +33,8 @@ struct Phys {
   double cv, lambda_l, lambda_v, dlam;  // dlam = (lambda_l - lambda_v)/(rho_l - rho_v)
   double t_side_val;
   double rho_ref;
-  int wall_mod;  // 1: modified-psi walls (the wall tables hold G_w)
+  int wall_mod;     // 1: modified-psi walls (the wall tables hold G_w)
+  int outflow_top;  // 1: the top row is a zero-gradient outflow, not a wall
 };
 
 // constants of the collision and the energy update in the compute type C

@@ -120,6 +120,7 @@ Phys make_phys(const lbm_params& p) {
   h.t_side_val = p.t_side_val;
   h.rho_ref = p.precision == LBM_FP32_SHIFTED ? p.rho_ref : 0.0;
   h.wall_mod = p.wall_model == LBM_WALL_MODIFIED_PSI ? 1 : 0;
+  h.outflow_top = p.outflow_top ? 1 : 0;
   return h;
 }
 
@@ -197,6 +198,11 @@ lbm_status lbm_validate(const lbm_params* p) {
   if (!std::isfinite(p->rho_ref)) return bad("rho_ref must be finite");
   if (p->wall_model != LBM_WALL_PSI_BASED && p->wall_model != LBM_WALL_MODIFIED_PSI)
     return bad("wall_model must be LBM_WALL_PSI_BASED or LBM_WALL_MODIFIED_PSI");
+  if (p->outflow_top != 0 && p->outflow_top != 1) return bad("outflow_top must be 0 or 1");
+  if (p->outflow_top && !p->walls) return bad("outflow_top needs walls (a wall at the bottom)");
+  if (p->outflow_top && p->gy != 0.0)
+    return fail(nullptr, LBM_E_UNSUPPORTED, "outflow_top with gravity is not implemented "
+                                            "(the mean density would change with the outflow)");
   return LBM_OK;
 }
 

@@ -243,9 +243,12 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
     gn[2] = kdn ? v2 : C(0);
     gn[5] = kdn ? v5 : C(0);
     gn[6] = kdn ? v6 : C(0);
-    gn[4] = kup ? v4 : C(0);
-    gn[7] = kup ? v7 : C(0);
-    gn[8] = kup ? v8 : C(0);
+    // zero-gradient outflow: the top row's populations from above are those
+    // of the row below, i.e. pulled from its own row (the clamped address)
+    const bool kin = kup || (WALLS && P.outflow_top);
+    gn[4] = kin ? v4 : C(0);
+    gn[7] = kin ? v7 : C(0);
+    gn[8] = kin ? v8 : C(0);
     Tn = C(ld(Tin + size_t(yr) * row_b, ox));
   };
 
@@ -313,7 +316,7 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
       const int yr = WALLS ? r : wrap3(r, ny);
       const double T = double(Tr);
       double rho, psi = 0.0;
-      if (WALLS && (yr == 0 || yr == ny - 1)) {
+      if (WALLS && (yr == 0 || (yr == ny - 1 && !P.outflow_top))) {
         const C gk = (yr == 0) ? g[0] + g[1] + g[3] + C(2) * (g[4] + g[7] + g[8])
                                : g[0] + g[1] + g[3] + C(2) * (g[2] + g[5] + g[6]);
         rho = rref + double(gk);
@@ -456,12 +459,19 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
 #pragma unroll
     for (int i = 0; i < 9; ++i) gp[i] = gin[i];
     const int ys = WALLS ? s : wrap3(s, ny);
-    const bool wb = WALLS && ys == 0, wt = WALLS && ys == ny - 1;
+    const bool wb = WALLS && ys == 0;
+    const bool wt = WALLS && ys == ny - 1 && !P.outflow_top;
+    const bool ot = WALLS && ys == ny - 1 && P.outflow_top;
     const double pc = s_psi[kc][lane];
     const double p1 = s_psi[kc][lp], p3 = s_psi[kc][lm];
     double p2, p5, p6, p4, p7, p8;
     if (wt) {
       p2 = p5 = p6 = psiw_t;
+    } else if (ot) {
+      // zero-gradient outflow: psi above the top row is the top row's own
+      p2 = pc;
+      p5 = p1;
+      p6 = p3;
     } else {
       p2 = s_psi[kq][lane];
       p5 = s_psi[kq][lp];
@@ -692,7 +702,7 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
         const int r = r0 + j;
         if (r < rend) {
           if (r == 1 && 0 >= rbase) closure(Ph<S1>{}, Ph<S0>{}, true);
-          if (r == ny - 1 && ny - 2 >= rbase) closure(Ph<S0>{}, Ph<S1>{}, false);
+          if (r == ny - 1 && ny - 2 >= rbase && !P.outflow_top) closure(Ph<S0>{}, Ph<S1>{}, false);
         }
       });
       stage_barrier();
@@ -780,7 +790,7 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
           stage_barrier();
           if (WALLS) {
             if (r == 1 && 0 >= rbase) closure(sr1, sr, true);
-            if (r == ny - 1 && ny - 2 >= rbase) closure(sr, sr1, false);
+            if (r == ny - 1 && ny - 2 >= rbase && !P.outflow_top) closure(sr, sr1, false);
             stage_barrier();
           }
           const int sB = r - 1;

@@ -597,3 +597,154 @@ def gw_search(meshes=(160, 240, 360, 540), target=125.9, N0=160, steps0=20000,
         if progress:
             progress(m + 1, len(meshes))
     return out
+
+
+STEFAN_SETS = {
+    # Sec. 4.2: first set = the droplet's c_v = 5 with both diffusivities
+    # 0.3; second set = c_v = 10, lambda_l = 15, lambda_v = 1
+    1: dict(cv=5.0, alpha=0.3),
+    2: dict(cv=10.0, lambda_l=15.0, lambda_v=1.0),
+}
+
+
+def stefan_mesh(L, set_id=2, L0=160, a0=6.12e-2, Tr=0.86, Tw_r=0.9, precision=0, tile_y=0):
+    """Mesh L of the 1-D boiling problem (Sec. 4.2) as one column of L
+    nodes along y: a Zou-He wall at y = 0 held at T_w = Tw_r T_c with the
+    psi-based rho_w = rho_v (hydrophobic), a zero-gradient outflow at the
+    top (adiabatic temperature), liquid at rest at T_sat = Tr T_c
+    everywhere at t = 0; a, sigma, kappa by the refinement rules with
+    dx = L0 / L; c_v and the conductivities of parameter set `set_id`.
+    Returns (params, boundary, rho, T, level record, thermal constants)."""
+    import numpy as np
+
+    from .sim import make_params, refinement_level
+
+    dx = L0 / L
+    lv = refinement_level(a0, dx, Tr, 0.0, 0.0)
+    st = STEFAN_SETS[set_id]
+    cv = st["cv"]
+    if "alpha" in st:
+        lam_l, lam_v = st["alpha"] * cv * lv["rho_l"], st["alpha"] * cv * lv["rho_v"]
+    else:
+        lam_l, lam_v = st["lambda_l"], st["lambda_v"]
+    rates = dict(s_rho=1.0, s_e=0.8, s_zeta=0.8, s_j=1.0, s_q=1.1)
+    p = make_params(1, L, a=lv["a"], sigma=lv["sigma"], kappa=lv["kappa"], rho_l=lv["rho_l"],
+                    rho_v=lv["rho_v"], walls=1, outflow_top=1, thermal=1, gy=0.0, cv=cv,
+                    lambda_l=lam_l, lambda_v=lam_v, eta_l=0.1, eta_v=0.1, rho_ref=lv["rho_l"],
+                    precision=precision, tile_y=tile_y, **rates)
+    Tw = Tw_r * lv["Tc"]
+    bnd = dict(rho_w_bottom=lv["rho_v"], rho_w_top=lv["rho_v"], t_bottom_kind=np.full(1, 1, np.int32),
+               t_bottom_val=Tw, t_top_kind=np.full(1, 2, np.int32), t_top_val=lv["T"])
+    rho = np.full((L, 1), lv["rho_l"])
+    T = np.full((L, 1), lv["T"])
+    th = dict(cv=cv, lambda_l=lam_l, lambda_v=lam_v, Tw=Tw, alpha_v=lam_v / (cv * lv["rho_v"]),
+              alpha_l=lam_l / (cv * lv["rho_l"]))
+    return p, bnd, rho, T, lv, th
+
+
+def stefan_front(rho_col, rho_l, rho_v):
+    """Interface position (nodes from the wall row): the last crossing of
+    (rho_l + rho_v) / 2 from vapour to liquid, linearly interpolated."""
+    import numpy as np
+
+    mid = 0.5 * (rho_l + rho_v)
+    r = np.asarray(rho_col, dtype=np.float64).ravel()
+    k = np.nonzero(r[:-1] < mid)[0]
+    if len(k) == 0:
+        return 0.0
+    k = int(k.max())
+    return float(k + (r[k] - mid) / (r[k] - r[k + 1]))
+
+
+def pr_latent_heat(lv, a, b=2.0 / 21.0, R=1.0, omega=0.344):
+    """Latent heat h_fg at the level's T_sat from the Peng-Robinson EOS:
+    the integral of T (dp/dT)_rho / rho^2 over [rho_v, rho_l] (64-point
+    Gauss-Legendre)."""
+    import math
+
+    import numpy as np
+
+    kw_ = 0.37464 + 1.54226 * omega - 0.2699 * omega * omega
+    Tc, T = lv["Tc"], lv["T"]
+    sa = 1.0 + kw_ * (1.0 - math.sqrt(T / Tc))
+    dalpha = -kw_ * sa / math.sqrt(T * Tc)  # d alpha / dT
+    xg, wg = np.polynomial.legendre.leggauss(64)
+    r = 0.5 * (lv["rho_l"] + lv["rho_v"]) + 0.5 * (lv["rho_l"] - lv["rho_v"]) * xg
+    dpdT = r * R / (1.0 - b * r) - a * dalpha * r * r / (1.0 + 2.0 * b * r - (b * r) ** 2)
+    return float(0.5 * (lv["rho_l"] - lv["rho_v"]) * (wg * T * dpdT / (r * r)).sum())
+
+
+def stefan_beta(ja):
+    """beta of Eq. stefan-analytical: beta exp(beta^2) erf(beta) = Ja / sqrt(pi)
+    (bisection)."""
+    import math
+
+    lo, hi = 0.0, 5.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if mid * math.exp(mid * mid) * math.erf(mid) * math.sqrt(math.pi) < ja:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def stefan_refinement(meshes=(160, 320, 640, 1280, 2560), sets=(1, 2), L0=160, steps0=40000,
+                      every0=200, precision=0, progress=None, **kw):
+    """Sec. 4.2 refinement: every (mesh, parameter set) column in one batch,
+    the front s(t) in base-mesh nodes sampled every every0 base-mesh steps
+    (the same physical times on every mesh), the relative change between
+    consecutive meshes sum_t |s_N - s_N*| / sum_t |s_N*| (as for Delta* R in
+    Sec. 4.1) with its convergence orders, and the similarity solution
+    2 beta sqrt(alpha_v t) (Eq. stefan-analytical) with the Jakob number
+    c_v (T_w - T_sat) / h_fg of each set."""
+    import math
+
+    import numpy as np
+
+    from .sim import Batch, Lattice
+
+    lats, info = [], []
+    for sid in sets:
+        for L in meshes:
+            p, bnd, rho, T, lv, th = stefan_mesh(L, sid, L0, precision=precision, **kw)
+            lat = Lattice(p)
+            lat.set_boundary(**bnd)
+            lat.init_fields(rho, None, None, T)
+            lats.append(lat)
+            info.append((sid, L, lv, th, p.a))
+    times = list(range(0, steps0 + 1, every0))
+    fronts = np.zeros((len(lats), len(times)))
+    b = Batch(lats)
+    done = [0] * len(lats)
+    for k, t in enumerate(times):
+        target = [int(round(t * (L / L0) ** 2)) for _, L, _, _, _ in info]
+        if k:
+            b.run([tg - d for tg, d in zip(target, done)])
+        done = target
+        for j, (lat, (_, L, lv, _, _)) in enumerate(zip(lats, info)):
+            fronts[j, k] = stefan_front(lat.fields()[0][:, 0], lv["rho_l"], lv["rho_v"]) * (L0 / L)
+        if progress and k % 20 == 0:
+            progress(k, len(times) - 1)
+    b.close()
+    for lat in lats:
+        lat.close()
+    out = {"meshes": list(meshes), "t": times, "sets": {}}
+    ratio = meshes[1] / meshes[0]
+    nm = len(meshes)
+    for si, sid in enumerate(sets):
+        rows = fronts[si * nm:(si + 1) * nm]
+        _, _, lv0, th0, a0_ = info[si * nm]
+        hfg = pr_latent_heat(lv0, a0_)
+        ja = th0["cv"] * (th0["Tw"] - lv0["T"]) / hfg
+        beta = stefan_beta(ja)
+        ref = 2.0 * beta * np.sqrt(th0["alpha_v"] * np.asarray(times, dtype=np.float64))
+        rel = [float(np.abs(rows[m] - rows[m + 1]).sum() / np.abs(rows[m + 1]).sum())
+               for m in range(nm - 1)]
+        out["sets"][sid] = {
+            "s": rows.tolist(), "reference": ref.tolist(), "ja": ja, "beta": beta,
+            "alpha_v": th0["alpha_v"], "alpha_l": th0["alpha_l"],
+            "rel_change": rel,
+            "orders": [math.log(rel[m] / rel[m + 1]) / math.log(ratio) for m in range(nm - 2)],
+            "rel_to_reference": [float(np.abs(r - ref).sum() / np.abs(ref).sum()) for r in rows]}
+    return out

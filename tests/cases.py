@@ -14,7 +14,8 @@ def oracle_params(c):
     keys = ["nx", "ny", "a", "sigma", "kappa", "s_rho", "s_e", "s_zeta", "s_j", "s_q", "eta_l",
             "eta_v", "rho_l", "rho_v", "gy", "walls", "thermal", "n_iso", "cv", "lambda_l",
             "lambda_v", "rho_w_bottom", "rho_w_top", "t_bottom_kind", "t_bottom_val", "t_top_kind",
-            "t_top_val", "t_side_dirichlet", "t_side_val", "wall_model", "gw_bottom", "gw_top"]
+            "t_top_val", "t_side_dirichlet", "t_side_val", "wall_model", "gw_bottom", "gw_top",
+            "outflow_top"]
     return Params(**{k: c[k] for k in keys if k in c})
 
 
@@ -24,7 +25,7 @@ def lib_params(c, precision=0, tile_y=0, rho_ref=None, xcd_remap=1, strip_waves=
     scal = ["a", "sigma", "kappa", "s_rho", "s_e", "s_zeta", "s_j", "s_q", "eta_l", "eta_v",
             "rho_l", "rho_v", "gy", "cv", "lambda_l", "lambda_v", "t_side_val"]
     kw = {k: float(c[k]) for k in scal if k in c}
-    for k in ("walls", "thermal", "n_iso", "t_side_dirichlet", "wall_model"):
+    for k in ("walls", "thermal", "n_iso", "t_side_dirichlet", "wall_model", "outflow_top"):
         if k in c:
             kw[k] = int(c[k])
     kw["precision"] = precision
@@ -62,7 +63,7 @@ def droplet128():
     return c, rho, Tf
 
 
-def random_tiny(nx, ny, seed, walls=False, thermal=False, gy=0.0, wall_model=0):
+def random_tiny(nx, ny, seed, walls=False, thermal=False, gy=0.0, wall_model=0, outflow_top=False):
     """Random near-equilibrium state inside the EOS domain, exercising every
     term: walls with random wall densities (or random G_w for modified-psi
     walls), mixed temperature kinds."""
@@ -74,6 +75,8 @@ def random_tiny(nx, ny, seed, walls=False, thermal=False, gy=0.0, wall_model=0):
     if walls:
         c["rho_w_bottom"] = rng.uniform(0.5, 6.0, nx)
         c["rho_w_top"] = rng.uniform(0.5, 6.0, nx)
+        if outflow_top:
+            c["outflow_top"] = True
         if wall_model == 1:
             c["wall_model"] = 1
             c["gw_bottom"] = rng.uniform(-1.4, -0.6, nx)

@@ -56,7 +56,7 @@ def test_validation(lib):
     bad = [dict(nx=0), dict(ny=0), dict(a=0.0), dict(b=-1.0), dict(s_e=2.0), dict(s_q=0.0),
            dict(precision=7), dict(walls=1, ny=2), dict(thermal=1, cv=0.0), dict(tile_y=1),
            dict(rho_l=1.0, rho_v=1.0), dict(G=1.0), dict(n_iso=-1), dict(wall_model=2),
-           dict(wall_model=-1), dict(strip_waves=3)]
+           dict(wall_model=-1), dict(strip_waves=3), dict(outflow_top=1), dict(outflow_top=2, walls=1)]
     for kw in bad:
         nx = kw.pop("nx", 16)
         ny = kw.pop("ny", 16)
@@ -65,6 +65,11 @@ def test_validation(lib):
         n = ctypes.c_size_t()
         assert lib.lbm_buffer_bytes(ctypes.byref(p), ctypes.byref(n)) == LBM_E_INVAL
     assert lib.lbm_validate(None) == LBM_E_INVAL
+    # an open top with gravity would need the outflow in the mean density
+    p = make_params(16, 16, walls=1, outflow_top=1, gy=-1e-5)
+    assert lib.lbm_validate(ctypes.byref(p)) == 6  # LBM_E_UNSUPPORTED
+    p = make_params(16, 16, walls=1, outflow_top=1)
+    assert lib.lbm_validate(ctypes.byref(p)) == LBM_OK
 
 
 def test_buffer_bytes_cover_state(lib):

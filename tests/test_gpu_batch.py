@@ -188,3 +188,27 @@ def test_contact_angle_models_under_refinement():
     print("G_w", g["gw"], flush=True)
     assert g["gw"][0] is not None and g["gw"][1] is not None
     assert -1.0 < g["gw"][1] < g["gw"][0] < -0.7
+
+
+def test_stefan_refinement_columns():
+    """Sec. 4.2 refinement on short columns (40, 80, 160 nodes over a 40
+    base, both parameter sets in one batch): the printed Jakob numbers, a
+    vapour film that grows from the hot wall on every mesh, and curves that
+    approach each other with refinement.  (On so short a column the open
+    end pressurises the liquid and the coarsest front turns back; the
+    similarity solution is only a loose reference here.)"""
+    print("case stefan refinement 40/80/160", flush=True)
+    from paper_2201_04560_amd.ladder import stefan_refinement
+
+    r = stefan_refinement((40, 80, 160), L0=40, steps0=4000, every0=100)
+    for sid in (1, 2):
+        d = r["sets"][sid]
+        print(sid, "rel", d["rel_change"], "vs ref", d["rel_to_reference"],
+              "s_end", np.asarray(d["s"])[:, -1], "ref_end", d["reference"][-1], flush=True)
+    for sid, ja in ((1, 0.038), (2, 0.076)):
+        d = r["sets"][sid]
+        s = np.asarray(d["s"])
+        assert abs(d["ja"] - ja) < 1e-3
+        assert np.all(s[:, 10] > 2.0) and np.all(s[:, 20] > s[:, 10])
+        assert d["rel_change"][1] < d["rel_change"][0] < 0.5
+        assert all(v < 0.6 for v in d["rel_to_reference"])

@@ -126,6 +126,64 @@ def test_droplet_on_modified_psi_wall(precision):
         assert _rel(r, ro) < 1e-3 and _rel(T2, To) < 1e-6
 
 
+@pytest.mark.parametrize("nx,ny,thermal,wall_model,waves", [
+    (7, 9, True, 0, 1),
+    (7, 9, True, 0, 2),
+    (9, 8, True, 1, 1),
+    (66, 7, False, 0, 1),
+    (1, 12, True, 0, 1),
+])
+def test_one_step_outflow_top(nx, ny, thermal, wall_model, waves):
+    """Zero-gradient outflow at the top row (1-D boiling problem, Sec. 4.2)
+    above a wall of either contact-angle model."""
+    print(f"case one_step outflow nx={nx} ny={ny} thermal={thermal} wall_model={wall_model} "
+          f"waves={waves}", flush=True)
+    c, rho, ux, uy, T = cases.random_tiny(nx, ny, seed=nx * 17 + ny, walls=True, thermal=thermal,
+                                          wall_model=wall_model, outflow_top=True)
+    s = _oracle(c, rho, ux, uy, T)
+    lat = _lat(c, strip_waves=waves)
+    lat.init_fields(rho, ux, uy, T)
+    _compare(lat, s, 1e-13, "init")
+    s.step(1)
+    lat.step(1)
+    _compare(lat, s, 1e-12, "step1")
+    s.step(4)
+    lat.step(4)
+    _compare(lat, s, 1e-11, "step5")
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_stefan_column_outflow(precision):
+    """The 1-D boiling column (second parameter set of Sec. 4.2 on 96 nodes,
+    one column): hot hydrophobic wall, liquid pushed out through the open
+    end; 800 steps."""
+    print(f"case stefan column precision={precision}", flush=True)
+    from oracle import thermo as th
+
+    a = 6.12e-2
+    eos = th.EOS(a)
+    Ts, Tw = 0.86 * eos.Tc, 0.9 * eos.Tc
+    rv, rl, _ = th.maxwell(eos, Ts)
+    nx, ny = 1, 96
+    c = dict(nx=nx, ny=ny, a=a, sigma=th.fit_sigma(eos, Ts), kappa=0.0, rho_l=rl, rho_v=rv,
+             walls=True, outflow_top=True, rho_w_bottom=rv, thermal=True, cv=10.0, lambda_l=15.0,
+             lambda_v=1.0, t_bottom_kind=np.full(nx, 1), t_bottom_val=np.full(nx, Tw),
+             t_top_kind=np.full(nx, 2), t_top_val=np.full(nx, Ts), **cases.wl.POOL_RATES)
+    rho, T = np.full((ny, nx), rl), np.full((ny, nx), Ts)
+    s = _oracle(c, rho, None, None, T)
+    lat = _lat(c, precision=precision)
+    lat.init_fields(rho, None, None, T)
+    s.step(800)
+    lat.step(800)
+    if precision == 0:
+        _compare(lat, s, 1e-10, "stefan@800")
+    else:  # float32 storage: loose agreement (its parity is unpinned)
+        r, T2 = lat.fields()[0], lat.fields()[3]
+        ro, To = s.fields()[0], s.fields()[3]
+        print("fp32 rho rel", _rel(r, ro), "T rel", _rel(T2, To), flush=True)
+        assert _rel(r, ro) < 1e-3 and _rel(T2, To) < 1e-5
+
+
 def test_droplet128_1000_steps_fp64():
     print("case droplet128 fp64 1000 steps", flush=True)
     c, rho, T = cases.droplet128()

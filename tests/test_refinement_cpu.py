@@ -107,3 +107,25 @@ def test_wall_droplet_meshes_follow_the_refinement_rules():
             # half disk of radius N/4 on the bottom wall
             assert rho[0, N // 2] > lv["rho_l"] - 1e-6 and rho[N // 4 + N // 8, N // 2] < lv["rho_v"] + 1e-3
             assert abs(rho[:, :N // 2].sum() - rho[:, N // 2:][:, ::-1].sum()) < 1e-9 * rho.sum()
+
+
+def test_stefan_meshes_and_jakob_numbers():
+    """Sec. 4.2: both parameter sets give the printed Jakob numbers (0.038,
+    0.076) and diffusivities (0.3 / 0.3; 0.23 / 0.26) on every mesh; beta
+    solves its transcendental equation."""
+    import math
+
+    from paper_2201_04560_amd.ladder import pr_latent_heat, stefan_beta, stefan_front, stefan_mesh
+
+    for sid, ja_p, al, av in ((1, 0.038, 0.3, 0.3), (2, 0.076, 0.23, 0.26)):
+        for L in (160, 320, 640):
+            p, bnd, rho, T, lv, th = stefan_mesh(L, sid)
+            assert p.outflow_top == 1 and p.nx == 1 and p.ny == L and p.gy == 0.0
+            ja = th["cv"] * (th["Tw"] - lv["T"]) / pr_latent_heat(lv, p.a)
+            assert abs(ja - ja_p) < 1e-3, (sid, L, ja)
+            assert abs(th["alpha_l"] - al) < 5e-3 and abs(th["alpha_v"] - av) < 5e-3
+            b = stefan_beta(ja)
+            assert abs(b * math.exp(b * b) * math.erf(b) * math.sqrt(math.pi) - ja) < 1e-12
+    r = np.r_[np.full(7, 0.38), [2.0, 5.0], np.full(20, 6.5)]
+    mid = 0.5 * (6.5 + 0.38)
+    assert abs(stefan_front(r, 6.5, 0.38) - (7 + (2.0 - mid) / (2.0 - 5.0))) < 1e-12
