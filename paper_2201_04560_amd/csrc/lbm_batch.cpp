@@ -47,7 +47,7 @@ struct lbm_batch {
   hipEvent_t join = nullptr, t0 = nullptr, t1 = nullptr;
   char* dev = nullptr;
   size_t bytes = 0;
-  int fp32 = 0, walls = 0;
+  int fp32 = 0, walls = 0, wall_mode = 0;
   size_t sdesc = 0, wdesc = 0;
   std::string err;
   bool timed = false;
@@ -106,6 +106,12 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int32_t n, void* dev_buf, size
   b->bytes = bytes;
   b->fp32 = fp32;
   b->walls = walls;
+  b->wall_mode = 0;
+  if (walls) {
+    b->wall_mode = 1;
+    for (int i = 0; i < n; ++i)
+      if (ctxs[i]->ph.wall_mod || ctxs[i]->ph.outflow_top) b->wall_mode = 2;
+  }
   b->sdesc = step_desc_bytes(fp32);
   b->wdesc = wall_desc_bytes(fp32);
   // graph capture needs a stream of its own (the caller's may be the null stream)
@@ -136,7 +142,7 @@ static lbm_status issue(lbm_batch* b, const LaunchRec& r, hipStream_t st) {
   if (r.wall_table >= 0)
     BTRY(b, launch_wall_multi(b->fp32, b->wall_tab(r.wall_table), b->wstarts(r.wall_table), r.ngrid,
                               r.wall_nblocks, st));
-  BTRY(b, launch_step_multi(b->fp32, b->walls, r.thermal, b->step_tab(r.table), b->starts(r.table), r.ngrid,
+  BTRY(b, launch_step_multi(b->fp32, b->wall_mode, r.thermal, b->step_tab(r.table), b->starts(r.table), r.ngrid,
                             r.nblocks, st));
   return LBM_OK;
 }

@@ -114,7 +114,9 @@ int wall_blocks(int nx);
 // filled on the host, copied to device memory and indexed by workgroup range
 size_t step_desc_bytes(int fp32);
 void fill_step_desc(const LaunchStep& L, void* out);
-hipError_t launch_step_multi(int fp32, int walls, int thermal, const void* desc, const int* start,
+// wall_mode: 0 periodic, 1 psi-based walls, 2 some lattice has modified-psi
+// walls or an outflow top
+hipError_t launch_step_multi(int fp32, int wall_mode, int thermal, const void* desc, const int* start,
                              int ngrid, int nblocks, hipStream_t st);
 size_t wall_desc_bytes(int fp32);
 void fill_wall_desc(const LaunchWall& L, void* out);

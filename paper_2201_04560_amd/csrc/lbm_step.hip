@@ -148,8 +148,16 @@ using Ph = std::integral_constant<int, N>;
 // later; they exchange rows through LDS rings of 8 rows and meet at one
 // workgroup barrier per row.  Handing the collision to wave 1 as well (21
 // values per node through LDS) measured slower on MI355X.
-template <class S, class C, bool WALLS, bool THERMAL, int MODE, int RPI, bool WS>
+// WM: 0 periodic in y, 1 Zou-He walls (psi-based), 2 walls with the modified-
+// psi model and/or the zero-gradient outflow top (runtime flags of Phys);
+// lattices without those features run the WM = 1 code, which does not carry
+// their branches.
+template <class S, class C, int WM, bool THERMAL, int MODE, int RPI, bool WS>
 __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroOut& O, const int bid) {
+  constexpr bool WALLS = WM != 0;
+  constexpr bool WX = WM == 2;
+  const bool wall_mod = WX && A.ph.wall_mod;
+  const bool outflow = WX && A.ph.outflow_top;
   static_assert(!WS || (MODE == MODE_STEP && THERMAL && RPI == 1), "two-wave march: energy step only");
   const int lane = WS ? int(threadIdx.x & (kLanes - 1)) : int(threadIdx.x);
   const int wave = WS ? __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)) : 0;
@@ -245,7 +253,7 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
     gn[6] = kdn ? v6 : C(0);
     // zero-gradient outflow: the top row's populations from above are those
     // of the row below, i.e. pulled from its own row (the clamped address)
-    const bool kin = kup || (WALLS && P.outflow_top);
+    const bool kin = kup || (WALLS && outflow);
     gn[4] = kin ? v4 : C(0);
     gn[7] = kin ? v7 : C(0);
     gn[8] = kin ? v8 : C(0);
@@ -316,7 +324,7 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
       const int yr = WALLS ? r : wrap3(r, ny);
       const double T = double(Tr);
       double rho, psi = 0.0;
-      if (WALLS && (yr == 0 || (yr == ny - 1 && !P.outflow_top))) {
+      if (WALLS && (yr == 0 || (yr == ny - 1 && !outflow))) {
         const C gk = (yr == 0) ? g[0] + g[1] + g[3] + C(2) * (g[4] + g[7] + g[8])
                                : g[0] + g[1] + g[3] + C(2) * (g[2] + g[5] + g[6]);
         rho = rref + double(gk);
@@ -351,7 +359,7 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
     const double Tw = double(s_T[SW][lane]);
     const double rw = A.tabd[(bottom ? 0 : 1) * nx + x];  // rho_w, or G_w (modified-psi)
     double psiw, rwall, psiwall;
-    if (P.wall_mod) {
+    if (wall_mod) {
       const double nbsum = s_psi[SN][lane] / 3.0 + (s_psi[SN][lp] + s_psi[SN][lm]) / 12.0;
       rwall = wall_density_mod(K, nbsum, rw, Tw, P);
       psiwall = psi_checked(rwall, Tw, P, err);
@@ -460,8 +468,8 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
     for (int i = 0; i < 9; ++i) gp[i] = gin[i];
     const int ys = WALLS ? s : wrap3(s, ny);
     const bool wb = WALLS && ys == 0;
-    const bool wt = WALLS && ys == ny - 1 && !P.outflow_top;
-    const bool ot = WALLS && ys == ny - 1 && P.outflow_top;
+    const bool wt = WALLS && ys == ny - 1 && !outflow;
+    const bool ot = WALLS && ys == ny - 1 && outflow;
     const double pc = s_psi[kc][lane];
     const double p1 = s_psi[kc][lp], p3 = s_psi[kc][lm];
     double p2, p5, p6, p4, p7, p8;
@@ -489,7 +497,7 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
     // Eq. shanchen (psi_w for solid neighbours: Eq. shanchen-walls)
     double d1 = p1 - pc, d2 = p2 - pc, d3 = p3 - pc, d4 = p4 - pc;
     double d5 = p5 - pc, d6 = p6 - pc, d7 = p7 - pc, d8 = p8 - pc;
-    if (WALLS && P.wall_mod) {
+    if (WALLS && wall_mod) {
       // Eq. Q-mod-psi-based: solid neighbours drop out of Q
       if (wb) d4 = d7 = d8 = 0.0;
       if (wt) d2 = d5 = d6 = 0.0;
@@ -702,7 +710,7 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
         const int r = r0 + j;
         if (r < rend) {
           if (r == 1 && 0 >= rbase) closure(Ph<S1>{}, Ph<S0>{}, true);
-          if (r == ny - 1 && ny - 2 >= rbase && !P.outflow_top) closure(Ph<S0>{}, Ph<S1>{}, false);
+          if (r == ny - 1 && ny - 2 >= rbase && !outflow) closure(Ph<S0>{}, Ph<S1>{}, false);
         }
       });
       stage_barrier();
@@ -790,7 +798,7 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
           stage_barrier();
           if (WALLS) {
             if (r == 1 && 0 >= rbase) closure(sr1, sr, true);
-            if (r == ny - 1 && ny - 2 >= rbase && !P.outflow_top) closure(sr, sr1, false);
+            if (r == ny - 1 && ny - 2 >= rbase && !outflow) closure(sr, sr1, false);
             stage_barrier();
           }
           const int sB = r - 1;
@@ -837,18 +845,18 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
   }
 }
 
-template <class S, class C, bool WALLS, bool THERMAL, int MODE>
+template <class S, class C, int WM, bool THERMAL, int MODE>
 __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(WavesPerEU<S>::value, 8)))
 void lbm_march_kernel(StepArgs<S, C> A, MacroOut O) {
-  march_body<S, C, WALLS, THERMAL, MODE, 1, false>(A, O, blockIdx.x);
+  march_body<S, C, WM, THERMAL, MODE, 1, false>(A, O, blockIdx.x);
 }
 
 // the energy step with two waves per strip (see march_body)
-template <class S, class C, bool WALLS>
+template <class S, class C, int WM>
 __global__ __launch_bounds__(2 * kLanes) __attribute__((amdgpu_waves_per_eu(WavesPerEU<S>::value, 8)))
 void lbm_march2_kernel(StepArgs<S, C> A) {
   const MacroOut O{};
-  march_body<S, C, WALLS, true, MODE_STEP, 1, true>(A, O, blockIdx.x);
+  march_body<S, C, WM, true, MODE_STEP, 1, true>(A, O, blockIdx.x);
 }
 
 // Batched launch over several lattices of one kind (same storage, walls and
@@ -856,7 +864,7 @@ void lbm_march2_kernel(StepArgs<S, C> A) {
 // arguments are read from the descriptor table in device memory.  Each
 // lattice's workgroup count is padded to a multiple of 8 so that the XCD of
 // a workgroup is the same as in a single-lattice launch.
-template <class S, class C, bool WALLS, bool THERMAL>
+template <class S, class C, int WM, bool THERMAL>
 __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(WavesPerEU<S>::value, 8)))
 void lbm_march_multi_kernel(const StepArgs<S, C>* __restrict__ desc, const int* __restrict__ start,
                             int ngrid) {
@@ -864,7 +872,7 @@ void lbm_march_multi_kernel(const StepArgs<S, C>* __restrict__ desc, const int* 
   int g = 0;
   while (g + 1 < ngrid && b >= start[g + 1]) ++g;
   const MacroOut O{};
-  march_body<S, C, WALLS, THERMAL, MODE_STEP, 1, false>(desc[g], O, b - start[g]);
+  march_body<S, C, WM, THERMAL, MODE_STEP, 1, false>(desc[g], O, b - start[g]);
 }
 
 // ------------------------------------------------------------- launchers
@@ -889,10 +897,23 @@ static PhysC<C> phys_c(const Phys& p) {
   return q;
 }
 
-template <class S, class C, bool WALLS, bool THERMAL, int MODE>
+template <class S, class C, int WM, bool THERMAL, int MODE>
 static void launch_one(const StepArgs<S, C>& a, const MacroOut& o, int nblocks, hipStream_t st) {
-  hipLaunchKernelGGL((lbm_march_kernel<S, C, WALLS, THERMAL, MODE>), dim3(nblocks), dim3(kLanes), 0,
+  hipLaunchKernelGGL((lbm_march_kernel<S, C, WM, THERMAL, MODE>), dim3(nblocks), dim3(kLanes), 0,
                      st, a, o);
+}
+
+// wall mode of a lattice: 0 periodic, 1 psi-based walls, 2 walls with the
+// modified-psi model or the outflow top
+static int wall_mode(int walls, const Phys& ph) {
+  return walls ? ((ph.wall_mod || ph.outflow_top) ? 2 : 1) : 0;
+}
+
+template <class S, class C, bool THERMAL, int MODE>
+static void launch_wm(int wm, const StepArgs<S, C>& a, const MacroOut& o, int nblocks, hipStream_t st) {
+  if (wm == 2) launch_one<S, C, 2, THERMAL, MODE>(a, o, nblocks, st);
+  else if (wm == 1) launch_one<S, C, 1, THERMAL, MODE>(a, o, nblocks, st);
+  else launch_one<S, C, 0, THERMAL, MODE>(a, o, nblocks, st);
 }
 
 template <class S, class C>
@@ -931,20 +952,20 @@ static hipError_t launch_step_t(const LaunchStep& L, hipStream_t st, int mode) {
   const StepArgs<S, C> a = make_args<S, C>(L);
   MacroOut o{L.o_rho, L.o_ux, L.o_uy, L.o_T, L.o_f, L.f_first, L.f_count};
   const int nb = L.ntx * L.nty;
+  const int wm = wall_mode(L.walls, L.ph);
   if (mode == MODE_MACRO) {
-    if (L.walls) launch_one<S, C, true, false, MODE_MACRO>(a, o, nb, st);
-    else launch_one<S, C, false, false, MODE_MACRO>(a, o, nb, st);
+    launch_wm<S, C, false, MODE_MACRO>(wm, a, o, nb, st);
   } else if (L.update_T && L.waves == 2) {
-    if (L.walls)
-      hipLaunchKernelGGL((lbm_march2_kernel<S, C, true>), dim3(nb), dim3(2 * kLanes), 0, st, a);
+    if (wm == 2)
+      hipLaunchKernelGGL((lbm_march2_kernel<S, C, 2>), dim3(nb), dim3(2 * kLanes), 0, st, a);
+    else if (wm == 1)
+      hipLaunchKernelGGL((lbm_march2_kernel<S, C, 1>), dim3(nb), dim3(2 * kLanes), 0, st, a);
     else
-      hipLaunchKernelGGL((lbm_march2_kernel<S, C, false>), dim3(nb), dim3(2 * kLanes), 0, st, a);
-  } else if (L.walls) {
-    if (L.update_T) launch_one<S, C, true, true, MODE_STEP>(a, o, nb, st);
-    else launch_one<S, C, true, false, MODE_STEP>(a, o, nb, st);
+      hipLaunchKernelGGL((lbm_march2_kernel<S, C, 0>), dim3(nb), dim3(2 * kLanes), 0, st, a);
+  } else if (L.update_T) {
+    launch_wm<S, C, true, MODE_STEP>(wm, a, o, nb, st);
   } else {
-    if (L.update_T) launch_one<S, C, false, true, MODE_STEP>(a, o, nb, st);
-    else launch_one<S, C, false, false, MODE_STEP>(a, o, nb, st);
+    launch_wm<S, C, false, MODE_STEP>(wm, a, o, nb, st);
   }
   return hipGetLastError();
 }
@@ -973,31 +994,31 @@ void fill_step_desc(const LaunchStep& L, void* out) {
   }
 }
 
-template <class S, class C, bool WALLS, bool THERMAL>
+template <class S, class C, int WM, bool THERMAL>
 static void launch_multi_t(const void* desc, const int* start, int ngrid, int nblocks, hipStream_t st) {
-  hipLaunchKernelGGL((lbm_march_multi_kernel<S, C, WALLS, THERMAL>), dim3(nblocks), dim3(kLanes), 0, st,
+  hipLaunchKernelGGL((lbm_march_multi_kernel<S, C, WM, THERMAL>), dim3(nblocks), dim3(kLanes), 0, st,
                      static_cast<const StepArgs<S, C>*>(desc), start, ngrid);
 }
 
-hipError_t launch_step_multi(int fp32, int walls, int thermal, const void* desc, const int* start,
-                             int ngrid, int nblocks, hipStream_t st) {
-  if (fp32) {
-    if (walls) {
-      if (thermal) launch_multi_t<float, float, true, true>(desc, start, ngrid, nblocks, st);
-      else launch_multi_t<float, float, true, false>(desc, start, ngrid, nblocks, st);
-    } else {
-      if (thermal) launch_multi_t<float, float, false, true>(desc, start, ngrid, nblocks, st);
-      else launch_multi_t<float, float, false, false>(desc, start, ngrid, nblocks, st);
-    }
+template <class S, class C>
+static void launch_multi_s(int wm, int thermal, const void* desc, const int* start, int ngrid,
+                           int nblocks, hipStream_t st) {
+  if (wm == 2) {
+    if (thermal) launch_multi_t<S, C, 2, true>(desc, start, ngrid, nblocks, st);
+    else launch_multi_t<S, C, 2, false>(desc, start, ngrid, nblocks, st);
+  } else if (wm == 1) {
+    if (thermal) launch_multi_t<S, C, 1, true>(desc, start, ngrid, nblocks, st);
+    else launch_multi_t<S, C, 1, false>(desc, start, ngrid, nblocks, st);
   } else {
-    if (walls) {
-      if (thermal) launch_multi_t<double, double, true, true>(desc, start, ngrid, nblocks, st);
-      else launch_multi_t<double, double, true, false>(desc, start, ngrid, nblocks, st);
-    } else {
-      if (thermal) launch_multi_t<double, double, false, true>(desc, start, ngrid, nblocks, st);
-      else launch_multi_t<double, double, false, false>(desc, start, ngrid, nblocks, st);
-    }
+    if (thermal) launch_multi_t<S, C, 0, true>(desc, start, ngrid, nblocks, st);
+    else launch_multi_t<S, C, 0, false>(desc, start, ngrid, nblocks, st);
   }
+}
+
+hipError_t launch_step_multi(int fp32, int wall_mode, int thermal, const void* desc, const int* start,
+                             int ngrid, int nblocks, hipStream_t st) {
+  if (fp32) launch_multi_s<float, float>(wall_mode, thermal, desc, start, ngrid, nblocks, st);
+  else launch_multi_s<double, double>(wall_mode, thermal, desc, start, ngrid, nblocks, st);
   return hipGetLastError();
 }
 
