@@ -321,6 +321,36 @@ def _pool_mesh3(precision, tile_y):
     return lat
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_vaporisation512_full_size_bench_launch(precision):
+    """The bench workload itself (512 x 512 droplet vaporisation, radius 60,
+    seed 0, ring held at 0.95 T_c) in the launch configuration the bench
+    times (5-row strips, two waves per strip): 20 steps against the oracle,
+    element by element over the whole lattice."""
+    print(f"case vaporisation512 full size precision={precision}", flush=True)
+    eos, Tsat, rv, rl = cases.coexistence()
+    Tout = 0.95 * eos.Tc
+    n = 512
+    c = dict(nx=n, ny=n, a=2.0 / 49.0, sigma=0.1, kappa=0.1, rho_l=rl, rho_v=rv, thermal=True,
+             cv=6.0, lambda_l=2 / 3, lambda_v=2 / 3, t_side_dirichlet=True, t_side_val=Tout,
+             t_bottom_kind=np.full(n, 1), t_bottom_val=np.full(n, Tout),
+             t_top_kind=np.full(n, 1), t_top_val=np.full(n, Tout), **cases.wl.DROPLET_RATES)
+    rho, T = cases.wl.droplet(n, n, 60.0, 4.6 / 5.0, rl, rv, Tsat, Tout, seed=0)
+    s = _oracle(c, rho, None, None, T)
+    lat = _lat(c, precision=precision, tile_y=5, strip_waves=2)
+    assert lat.tile_y == 5 and lat.strip_waves == 2
+    lat.init_fields(rho, None, None, T)
+    s.step(20)
+    lat.step(20)
+    if precision == 0:
+        _compare(lat, s, 1e-11, "vaporisation512@20")
+    else:  # float32 storage: loose agreement (its parity is unpinned)
+        r, _, _, T2 = lat.fields()
+        ro, _, _, To = s.fields()
+        print("fp32 rho rel", _rel(r, ro), "T rel", _rel(T2, To), flush=True)
+        assert _rel(r, ro) < 1e-4 and _rel(T2, To) < 1e-6
+
+
 def test_pool_1024x2048_full_size_properties():
     """Full-size pool boiling in the launch configurations the autotuner
     picks from: float64 results agree across strip heights (only the order
