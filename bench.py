@@ -390,7 +390,13 @@ def pool_heat_flux(precision, steps, every, tune):
     r = lat.fields()[0]
     lat.close()
     torch.cuda.empty_cache()
-    return np.array(q), r, nx * ny * steps / dt / 1e6, kw
+    # Nusselt number of the heater: the mean wall heat flux over the heater
+    # (Q of Eq. pool-heat-flux times L / L_h) made dimensionless with the
+    # heater length L_h and the liquid conduction scale lambda_l (T_h - T_sat)
+    tb = np.broadcast_to(np.asarray(bnd["t_bottom_val"], dtype=np.float64), (nx,))
+    t_h, t_sat = float(tb.max()), float(np.min(bnd["t_top_val"]))
+    nu_scale = -nx / (kw["lambda_l"] * (t_h - t_sat))
+    return np.array(q), r, nx * ny * steps / dt / 1e6, dict(kw, nu_scale=nu_scale)
 
 
 def accuracy_bench(vap_res, case, args, tune):
@@ -417,11 +423,14 @@ def accuracy_bench(vap_res, case, args, tune):
     out["vaporisation512"]["fp32_rho_ref_mean"] = st
     steps, every = args.pool_steps, max(args.pool_steps // 10, 1)
     q32, p32, m32, _ = pool_heat_flux(1, steps, every, tune)
-    q64, p64, m64, _ = pool_heat_flux(0, steps, every, tune)
+    q64, p64, m64, k64 = pool_heat_flux(0, steps, every, tune)
+    nu32, nu64 = q32 * k64["nu_scale"], q64 * k64["nu_scale"]
     out["pool1024x2048"] = {
         "steps": steps, "q_in_every": every,
         "q_in_fp32": q32.tolist(), "q_in_fp64": q64.tolist(),
         "q_in_max_rel_diff": float(np.abs(q32 - q64).max() / np.abs(q64).max()),
+        "nusselt_heater_fp32": np.round(nu32, 6).tolist(), "nusselt_heater_fp64": np.round(nu64, 6).tolist(),
+        "nusselt_max_rel_diff": float(np.abs(nu32 - nu64).max() / np.abs(nu64).max()),
         "rho_max_rel": rel_err(p32, p64),
         "MLUPS_fp32_with_norms": round(m32, 1), "MLUPS_fp64_with_norms": round(m64, 1)}
     return out
