@@ -20,7 +20,9 @@ Modules
               Stefan similarity constant (Secs. 2, 3, 4.2)
   step     -- one full time step of the method: moments, pseudopotential
               forces, Li source terms, MRT collision, energy equation (RK2),
-              streaming with Zou-He walls (Sec. 2)
+              streaming with Zou-He walls of either contact-angle model
+              (psi-based or modified-psi) and the zero-gradient outflow of
+              the 1-D boiling problem (Secs. 2, 4.2)
   adjoint  -- reverse-mode derivative of the step (for the adjoint checks)
 
 Parity status of each function is stated in its module header.

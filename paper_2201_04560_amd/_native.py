@@ -11,6 +11,7 @@ c_int32, c_int64, c_double, c_size_t, c_void_p = (ctypes.c_int32, ctypes.c_int64
 LBM_OK, LBM_E_INVAL, LBM_E_NOMEM, LBM_E_HIP, LBM_E_STATE, LBM_E_DOMAIN, LBM_E_UNSUPPORTED = range(7)
 LBM_FP64, LBM_FP32_SHIFTED = 0, 1
 T_FREE, T_DIRICHLET, T_ADIABATIC = 0, 1, 2
+LBM_WALL_PSI_BASED, LBM_WALL_MODIFIED_PSI = 0, 1  # contact-angle models (lbm_params.wall_model)
 
 
 class LbmParams(ctypes.Structure):
