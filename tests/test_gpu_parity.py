@@ -351,6 +351,41 @@ def test_vaporisation512_full_size_bench_launch(precision):
         assert _rel(r, ro) < 1e-4 and _rel(T2, To) < 1e-6
 
 
+def test_huge_lattice_equals_tiled_small_one():
+    """A 16384 x 16384 lattice (268 M nodes, 21 GB of float32 populations
+    and temperatures, offsets far beyond 32 bits) started from a periodic
+    512 x 512 thermal droplet pattern tiled 32 x 32 times: without gravity
+    every node's arithmetic is that of the 512 x 512 run, so after 6 steps
+    every tile equals it bit for bit (whatever strip shapes either size
+    picks)."""
+    print("case huge 16384^2 tiled fp32", flush=True)
+    import torch
+
+    eos, Tsat, rv, rl = cases.coexistence()
+    n, k = 512, 32
+    c = dict(nx=n, ny=n, a=2.0 / 49.0, sigma=0.1, kappa=0.1, rho_l=rl, rho_v=rv, thermal=True,
+             cv=6.0, lambda_l=2 / 3, lambda_v=2 / 3, **cases.wl.DROPLET_RATES)
+    rho, T = cases.wl.droplet(n, n, 60.0, 4.6 / 5.0, rl, rv, Tsat, 0.95 * eos.Tc, seed=2)
+    small = _lat(c, precision=1)
+    small.init_fields(rho, None, None, T)
+    small.step(6)
+    r_s, ux_s, _, T_s = small.fields()
+    small.close()
+    del small
+    big_c = dict(c, nx=n * k, ny=n * k)
+    big = _lat(big_c, precision=1)
+    print("huge lattice allocated, tile_y", big.tile_y, "waves", big.strip_waves, flush=True)
+    big.init_fields(np.tile(rho, (k, k)), None, None, np.tile(T, (k, k)))
+    big.step(6)
+    r_b, ux_b, _, T_b = big.fields()
+    big.close()
+    del big
+    torch.cuda.empty_cache()
+    for a_b, a_s in ((r_b, r_s), (ux_b, ux_s), (T_b, T_s)):
+        blocks = a_b.reshape(k, n, k, n).transpose(0, 2, 1, 3)
+        assert np.array_equal(blocks, np.broadcast_to(a_s, blocks.shape))
+
+
 def test_pool_1024x2048_full_size_properties():
     """Full-size pool boiling in the launch configurations the autotuner
     picks from: float64 results agree across strip heights (only the order
