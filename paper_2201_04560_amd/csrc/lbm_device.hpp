@@ -33,6 +33,7 @@ struct Phys {
   double cv, lambda_l, lambda_v, dlam;  // dlam = (lambda_l - lambda_v)/(rho_l - rho_v)
   double t_side_val;
   double rho_ref;
+  double two_G;     // 2 / G: the radicand of Eq. psi without a division
   int wall_mod;     // 1: modified-psi walls (the wall tables hold G_w)
   int outflow_top;  // 1: the top row is a zero-gradient outflow, not a wall
 };
@@ -144,7 +145,7 @@ __device__ __forceinline__ EosNode eos_node(double rho, double T, const Phys& p)
   e.rsqT = rsq64(T);
   const double sa = 1.0 + p.kw * (1.0 - T * e.rsqT * p.inv_sqrtTc);
   const double pr = e.A1 * T - p.a * (sa * sa) * e.A2;
-  e.rad = 2.0 * (pr - rho * (1.0 / 3.0)) / p.G;
+  e.rad = (pr - rho * (1.0 / 3.0)) * p.two_G;
   return e;
 }
 // psi = sqrt(rad) with the domain checks of the method

@@ -119,6 +119,7 @@ Phys make_phys(const lbm_params& p) {
   h.dlam = (p.lambda_l - p.lambda_v) / (p.rho_l - p.rho_v);
   h.t_side_val = p.t_side_val;
   h.rho_ref = p.precision == LBM_FP32_SHIFTED ? p.rho_ref : 0.0;
+  h.two_G = 2.0 / p.G;  // exact for G = -1: the same bits as dividing 2 (p - rho / 3) by G
   h.wall_mod = p.wall_model == LBM_WALL_MODIFIED_PSI ? 1 : 0;
   h.outflow_top = p.outflow_top ? 1 : 0;
   return h;
