@@ -17,10 +17,14 @@
 //   C(r-2)  first RK2 stage of the energy equation -> T*   Eq. energy-equation
 //   D(r-3)  second RK2 stage -> T^{n+1}, store
 //
-// The workgroup is a single wavefront, and LDS operations of one wavefront
-// complete in program order, so the stages are separated by compiler-only
-// barriers: no s_barrier / memory fence that would also drain the
-// prefetched global loads.
+// In the one-wave march the workgroup is a single wavefront, and LDS
+// operations of one wavefront complete in program order, so the stages are
+// separated by compiler-only barriers: no s_barrier / memory fence that
+// would also drain the prefetched global loads.  The two-wave march (the
+// energy step on small lattices) gives C and D to a second wave one row
+// behind, with one workgroup barrier per row.  Each kernel is instantiated
+// for three wall modes: periodic in y, psi-based Zou-He walls, and walls
+// with the modified-psi model or the zero-gradient outflow top.
 //
 // Storage S is double (plain step) or float (populations stored as
 // g_i = f_i - w_i rho_ref).  C is the type of the collision and energy
