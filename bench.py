@@ -152,6 +152,92 @@ def measured_traffic(key, tile_y, waves):
         return None
 
 
+KERNEL_SOURCES = ["paper_2201_04560_amd/csrc/lbm_step.hip", "paper_2201_04560_amd/csrc/lbm_device.hpp",
+                  "paper_2201_04560_amd/csrc/lbm_kernels.hpp"]
+PROFILE_NODES = {"vaporisation512": 512 * 512, "pool4096": 4096 * 4096}
+
+
+def write_traffic(pmc_dir, copy_mib):
+    """Build profiles/traffic.json from rocprofv3 --pmc runs of the profile
+    mode: one directory per counter, named pmc_<case>_<prec>_<TY>x<W>_<CTR>
+    (CTR FETCH_SIZE or WRITE_SIZE), each holding run_counter_collection.csv.
+    Each counter is scaled by what it reads for the largest device copy of
+    the same run (copy_mib MiB read and written) and averaged over the
+    step-kernel dispatches."""
+    import csv
+    import glob
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    per = {}
+    for f in sorted(glob.glob(os.path.join(pmc_dir, "pmc_*", "run_counter_collection.csv"))):
+        parts = os.path.basename(os.path.dirname(f))[4:].split("_")
+        case, cfg, ctr = "_".join(parts[:2]), parts[2], "_".join(parts[3:])
+        with open(f) as fh:
+            rows = list(csv.DictReader(fh))
+        march = [float(r["Counter_Value"]) for r in rows if "lbm_march" in r["Kernel_Name"]]
+        copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        big = max(int(r["Grid_Size"]) for r in copies)
+        cal = [float(r["Counter_Value"]) for r in copies if int(r["Grid_Size"]) == big]
+        per.setdefault(case, {}).setdefault(cfg, {})[ctr] = dict(
+            kib=sum(march) / len(march), scale=copy_mib * 1024.0 / (sum(cal) / len(cal)),
+            n=len(march))
+    out = {"kernel_sha256": h.hexdigest(), "kernel_sources": KERNEL_SOURCES,
+           "calibration": f"each counter scaled by its KiB per dispatch of a {copy_mib} MiB "
+                          "device copy (that many KiB read and written)",
+           "per_launch_bytes": {}, "detail": {}}
+    for case, cfgs in sorted(per.items()):
+        alg = alg_bytes_per_node(case.endswith("fp32")) * PROFILE_NODES[case.split("_")[0]]
+        for cfg, c in sorted(cfgs.items()):
+            rd = c["FETCH_SIZE"]["kib"] * c["FETCH_SIZE"]["scale"] * 1024
+            wr = c["WRITE_SIZE"]["kib"] * c["WRITE_SIZE"]["scale"] * 1024
+            out["per_launch_bytes"].setdefault(case, {})[cfg] = int(round(rd + wr))
+            out["detail"].setdefault(case, {})[cfg] = {
+                "read_bytes": int(round(rd)), "write_bytes": int(round(wr)),
+                "algorithmic_bytes": alg, "ratio": round((rd + wr) / alg, 4),
+                "fetch_kib_raw": round(c["FETCH_SIZE"]["kib"], 1),
+                "write_kib_raw": round(c["WRITE_SIZE"]["kib"], 1),
+                "fetch_scale": round(c["FETCH_SIZE"]["scale"], 4),
+                "write_scale": round(c["WRITE_SIZE"]["scale"], 4),
+                "dispatches": c["FETCH_SIZE"]["n"]}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    return out
+
+
+def copy_bandwidth(mib=2048, reps=5):
+    """Measured device-to-device copy bandwidth (GB/s, bytes read + written),
+    the practical ceiling next to the 8 TB/s data-sheet figure."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    bw = reps * 2 * n * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return round(bw, 1)
+
+
+def with_copy_fraction(rl, copy_gbs):
+    """Roofline record plus the fraction of the measured copy bandwidth."""
+    if copy_gbs:
+        rl["copy_GBps"] = copy_gbs
+        rl["frac_of_copy"] = round(rl["achieved"] / copy_gbs, 4)
+    return rl
+
+
 def cpu_baseline(case, budget_s=15.0):
     """The float64 oracle on the host, one core, a bounded number of steps."""
     try:
@@ -466,6 +552,12 @@ def main():
                          "plus a device copy of --copy-mib MiB (counter calibration); no JSON")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--tile-y", type=int, default=0)
+    ap.add_argument("--strip-waves", type=int, default=0,
+                    help="waves per strip with --tile-y (0: the library's choice)")
+    ap.add_argument("--traffic-from", default=None, metavar="DIR",
+                    help="no GPU work: write profiles/traffic.json from the rocprofv3 --pmc "
+                         "directories DIR/pmc_<case>_<prec>_<TY>x<W>_<FETCH_SIZE|WRITE_SIZE> "
+                         "of --profile-case runs (calibration copy of --copy-mib MiB)")
     ap.add_argument("--ladder-steps0", type=int, default=50,
                     help="steps of the coarsest ladder mesh (mesh k runs steps0 * 4^k)")
     ap.add_argument("--no-ladder", action="store_true")
@@ -491,6 +583,12 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="library default strip heights instead of the autotuner")
     args = ap.parse_args()
+    if args.traffic_from:
+        for case, cfgs in write_traffic(args.traffic_from, args.copy_mib)["detail"].items():
+            for cfg, d in cfgs.items():
+                log(f"traffic: {case} {cfg} {(d['read_bytes'] + d['write_bytes']) / 1e6:.2f} MB "
+                    f"per launch, {d['ratio']}x algorithmic")
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "a multi-GPU slab decomposition is described in DESIGN.md but not built", file=sys.stderr)
@@ -510,9 +608,10 @@ def main():
         for name, prec in (("fp32", LBM_FP32_SHIFTED), ("fp64", LBM_FP64)):
             if args.only in (name, "both"):
                 r = run_lattice(pcase, prec, args.warmup, args.steps, want_fields=False,
-                                tile_y=args.tile_y, tune=tune)
+                                tile_y=args.tile_y, tune=tune, strip_waves=args.strip_waves)
                 log(f"profile: {args.profile_case} {name} kernel {r['kernel_ms_avg'] * 1e3:.2f} us "
-                    f"avg over {r['launches']} launches")
+                    f"avg over {r['launches']} launches, tile_y {r['tile_y']}, "
+                    f"waves {r['strip_waves']}")
         if args.copy_mib > 0:
             n = args.copy_mib * (1 << 20) // 4
             src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -563,6 +662,9 @@ def main():
                              measured_traffic(f"vaporisation512_{main_name}", m["tile_y"],
                                               m["strip_waves"])),
     }
+    copy_gbs = copy_bandwidth()
+    log(f"bench: device copy {copy_gbs} GB/s")
+    with_copy_fraction(out["roofline"], copy_gbs)
     if "fp32" in res and "fp64" in res:
         f32, f64 = res["fp32"], res["fp64"]
         r32, _, _, T32 = f32["fields"]
@@ -571,8 +673,10 @@ def main():
             "value": round(args.steps * nodes / f64["wall_s"] / 1e6, 1), "unit": "MLUPS",
             "tile_y": f64["tile_y"], "strip_waves": f64["strip_waves"],
             "ms_per_step": round(f64["wall_s"] * 1e3 / args.steps, 5),
-            "roofline": roofline(False, nodes, f64["kernel_ms_avg"],
-                                 measured_traffic("vaporisation512_fp64", f64["tile_y"], f64["strip_waves"])),
+            "roofline": with_copy_fraction(
+                roofline(False, nodes, f64["kernel_ms_avg"],
+                         measured_traffic("vaporisation512_fp64", f64["tile_y"], f64["strip_waves"])),
+                copy_gbs),
         }
         out["speedup_fp32_vs_fp64"] = round(f64["wall_s"] / f32["wall_s"], 3)
         out["fp32_error_vs_fp64"] = {
@@ -597,9 +701,11 @@ def main():
             sz[name] = {"value": round(args.sizing_steps * n2 / r["wall_s"] / 1e6, 1),
                         "unit": "MLUPS",
                         "tile_y": r["tile_y"], "strip_waves": r["strip_waves"],
-                        "roofline": roofline(name == "fp32", n2, r["kernel_ms_avg"],
-                                             measured_traffic(f"pool4096_{name}", r["tile_y"],
-                                                              r["strip_waves"]))}
+                        "roofline": with_copy_fraction(
+                            roofline(name == "fp32", n2, r["kernel_ms_avg"],
+                                     measured_traffic(f"pool4096_{name}", r["tile_y"],
+                                                      r["strip_waves"])),
+                            copy_gbs)}
         out["hbm_sized_run"] = {"workload": "pool boiling 4096x4096 (walls, heater, gravity, "
                                             "energy equation; mesh 5 of the refinement procedure "
                                             "over a 128x128 base), 1.3 GB f32 / 2.7 GB f64 state",
