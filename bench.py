@@ -590,8 +590,8 @@ def main():
                     f"per launch, {d['ratio']}x algorithmic")
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "a multi-GPU slab decomposition is described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py: the step runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU slab decomposition is designed but not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -50,7 +50,7 @@ typedef enum {
   LBM_E_HIP = 3,         /* HIP runtime error (text in lbm_last_error) */
   LBM_E_STATE = 4,       /* call out of order (e.g. step before init) */
   LBM_E_DOMAIN = 5,      /* state left the EOS / pseudopotential domain */
-  LBM_E_UNSUPPORTED = 6  /* valid request this build does not implement */
+  LBM_E_UNSUPPORTED = 6  /* valid request the library does not implement */
 } lbm_status;
 
 enum { LBM_FP64 = 0, LBM_FP32_SHIFTED = 1 };          /* storage precision */
