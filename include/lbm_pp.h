@@ -228,6 +228,18 @@ lbm_status lbm_batch_last_time(lbm_batch* b, double* ms, int64_t* kernel_launche
  * initialised like the real one. */
 lbm_status lbm_autotune_tile_y(lbm_ctx* ctx, const int32_t* candidates, int32_t n, int32_t steps,
                                int32_t* best_tile_y, double* best_ms_per_step);
+/* Strip heights that fill whole rounds of wave slots on the context's GPU:
+ * for m = 1..16 waves per SIMD (4 SIMDs per compute unit), the smallest
+ * tile_y whose launch of column tiles x strips x waves (waves per strip;
+ * 0 = the context's current setting) fits in m x 4 x compute units.  A
+ * launch just under such a multiple leaves no SIMD with one wave more than
+ * the others.  Ascending, distinct, each in [2, max(ny, 2)].  Writes
+ * min(count, cap) heights to out (out may be NULL with cap 0) and the count
+ * to *count.  LBM_E_INVAL for a null ctx or count, waves outside 0..2 or a
+ * negative cap; LBM_E_HIP if the device cannot be queried.  Host only; no
+ * GPU work. */
+lbm_status lbm_tile_candidates(const lbm_ctx* ctx, int32_t waves, int32_t* out, int32_t cap,
+                               int32_t* count);
 
 /* ---- host parameter pipeline (Sec. 3); float64, no GPU ----------------- */
 /* T_c of Eq. peng-robinson's a = 0.45724 R^2 T_c^2/p_c, b = 0.0778 R T_c/p_c */

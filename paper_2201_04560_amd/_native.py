@@ -79,6 +79,7 @@ SIGNATURES = [
     ("lbm_batch_run", c_int32, [c_void_p, P(c_int64), c_int32]),
     ("lbm_batch_last_time", c_int32, [c_void_p, _DP, P(c_int64), P(c_int64)]),
     ("lbm_autotune_tile_y", c_int32, [c_void_p, P(c_int32), c_int32, c_int32, P(c_int32), _DP]),
+    ("lbm_tile_candidates", c_int32, [c_void_p, c_int32, P(c_int32), c_int32, P(c_int32)]),
     ("lbm_refinement_level", c_int32, [c_double] * 9 + [c_int64, P(LbmLevel)]),
     ("lbm_adjoint_bytes", c_int32, [P(LbmParams), c_int32, c_int32, P(c_size_t)]),
     ("lbm_adjoint_create", c_int32, [c_void_p, c_int32, c_int32, c_double, c_double, c_void_p, c_size_t,

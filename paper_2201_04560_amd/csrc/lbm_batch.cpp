@@ -377,4 +377,31 @@ lbm_status lbm_autotune_tile_y(lbm_ctx* c, const int32_t* cand, int32_t n, int32
   return lbm_sync(c);
 }
 
+lbm_status lbm_tile_candidates(const lbm_ctx* c, int32_t waves, int32_t* out, int32_t cap,
+                               int32_t* count) {
+  if (!c || !count || waves < 0 || waves > 2 || cap < 0) return LBM_E_INVAL;
+  if (waves == 0) waves = lbm_get_strip_waves(c);
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, c->base) != hipSuccess) return LBM_E_HIP;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, attr.device) != hipSuccess ||
+      cus < 1)
+    return LBM_E_HIP;
+  constexpr int kSimdsPerCU = 4;
+  const int ny = c->p.ny, hi = std::max(ny, 2);
+  const long long per_strip = static_cast<long long>(c->L.ntx) * waves;
+  std::vector<int32_t> h;
+  for (int m = 1; m <= 16; ++m) {
+    const long long strips = static_cast<long long>(m) * kSimdsPerCU * cus / per_strip;
+    if (strips < 1) continue;
+    const int ty = static_cast<int>(std::min<long long>(hi, std::max<long long>(2, (ny + strips - 1) / strips)));
+    h.push_back(ty);
+  }
+  std::sort(h.begin(), h.end());
+  h.erase(std::unique(h.begin(), h.end()), h.end());
+  for (int k = 0; k < static_cast<int>(h.size()) && k < cap; ++k) out[k] = h[k];
+  *count = static_cast<int32_t>(h.size());
+  return LBM_OK;
+}
+
 }  // extern "C"

@@ -84,16 +84,22 @@ class TileCache:
         either way.  Returns (tile_y, strip_waves)."""
         hit = self.lookup(lattice.p, device)
         if hit is None:
-            best = None
+            best, tried = None, set()
             for w in (waves if lattice.p.thermal else (1,)):
                 lattice.strip_waves = w
-                ty, ms = lattice.autotune_tile_y(candidates, steps)
+                # the fixed ladder plus the heights that fill whole rounds of
+                # wave slots (a launch a few waves over such a round leaves
+                # some SIMDs with one wave more: 4096^2 float32 pool 128 rows
+                # -> 514 us, 100 rows -> 433 us on MI355X)
+                cand = sorted(set(candidates) | set(lattice.tile_candidates(w)))
+                tried.update(cand)
+                ty, ms = lattice.autotune_tile_y(cand, steps)
                 if best is None or ms < best[2]:
                     best = (ty, w, ms)
             hit = best[:2]
             self.table[self.key(lattice.p, device)] = {"tile_y": best[0], "strip_waves": best[1],
                                                        "ms_per_step": best[2],
-                                                       "candidates": list(candidates)}
+                                                       "candidates": sorted(tried)}
             self._save()
         lattice.tile_y, lattice.strip_waves = hit
         return hit

@@ -170,6 +170,18 @@ class Lattice:
     def strip_waves(self, w):
         check(lib().lbm_set_strip_waves(self._ctx, int(w)), self._ctx, "lbm_set_strip_waves")
 
+    def tile_candidates(self, waves=0):
+        """Strip heights whose launches fill whole rounds of wave slots on
+        this GPU (1..16 waves per SIMD), for `waves` waves per strip (0: the
+        current setting).  Ascending."""
+        n = ctypes.c_int32()
+        check(lib().lbm_tile_candidates(self._ctx, int(waves), None, 0, ctypes.byref(n)), self._ctx,
+              "lbm_tile_candidates")
+        out = (ctypes.c_int32 * max(n.value, 1))()
+        check(lib().lbm_tile_candidates(self._ctx, int(waves), out, n.value, ctypes.byref(n)),
+              self._ctx, "lbm_tile_candidates")
+        return [int(v) for v in out[:n.value]]
+
     def autotune_tile_y(self, candidates=(2, 3, 4, 6, 8, 12, 16, 24, 32), steps=20):
         """Time each candidate strip height on this lattice and keep the
         fastest.  The state is saved first and restored afterwards, so the

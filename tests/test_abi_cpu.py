@@ -95,6 +95,8 @@ def test_create_rejects_bad_buffers(lib):
                           ctypes.byref(ctx)) == LBM_E_INVAL
     assert b"aligned" in lib.lbm_last_error(None)
     assert lib.lbm_status_string(5) == b"state left the EOS / pseudopotential domain"
+    n = ctypes.c_int32()
+    assert lib.lbm_tile_candidates(None, 0, None, 0, ctypes.byref(n)) == LBM_E_INVAL
 
 
 @pytest.mark.parametrize("a", [2.0 / 49.0, 6.12e-2 * (128 / 288) ** 2])

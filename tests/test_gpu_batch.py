@@ -131,6 +131,30 @@ def test_autotune_keeps_state():
     assert np.array_equal(ref.populations(), lat.populations())
 
 
+def test_tile_candidates_fill_whole_rounds():
+    """Each candidate height is the smallest whose launch fits a whole number
+    of wave rounds (m waves on each of the 4 SIMDs of every compute unit)."""
+    print("case tile candidates", flush=True)
+    import torch
+
+    lat = _make(_pool_case(600, 300, 3, gy=0.0))  # walls: 56-column tiles, 11 of them
+    slots = 4 * torch.cuda.get_device_properties(0).multi_processor_count
+    for w in (1, 2):
+        got = lat.tile_candidates(w)
+        print(f"waves {w}: {got}", flush=True)
+        assert got and got == sorted(set(got)) and all(2 <= t <= 300 for t in got)
+
+        def waves(t):
+            return 11 * (-(-300 // t)) * w
+
+        for t in got:
+            assert any(waves(t) <= m * slots and (t == 2 or waves(t - 1) > m * slots)
+                       for m in range(1, 17))
+        rounds = {m for m in range(1, 17) if m * slots >= 11 * w}
+        assert len(got) <= len(rounds)
+    assert lat.tile_candidates(0) == lat.tile_candidates(lat.strip_waves)
+
+
 def test_droplet_refinement_converges():
     """Sec. 4.1 refinement on three meshes (64, 96, 144; a, sigma, kappa by
     the Sec. 3 rules, Delta t ~ Delta x^2) in one batch: the droplet radius
