@@ -70,7 +70,10 @@ typedef struct lbm_params {
   int32_t thermal;     /* 1: solve the energy equation */
   int32_t n_iso;       /* the first n_iso steps keep T frozen (Sec. 4.1) */
   int32_t t_side_dirichlet; /* 1: columns 0 and nx-1 held at t_side_val */
-  int32_t tile_y;      /* rows per workgroup strip; 0 = library default */
+  int32_t tile_y;      /* rows per workgroup strip; 0 = library default: 5 on
+                          small lattices, else the smallest height whose launch
+                          fits 3 (float32) / 2 (float64) waves per SIMD of the
+                          buffer's device */
   double a, b, R, omega, G;      /* Eq. peng-robinson, Eq. psi (G = -1) */
   double sigma, kappa;           /* Eqs. S and Q */
   double s_rho, s_e, s_zeta, s_j, s_q;   /* MRT rates; s_nu from eta(rho) */

@@ -32,9 +32,9 @@ bool small_lattice(int nx, int ny, int walls) {
 }
 
 int default_tile_y(int nx, int ny, int walls, int fp32) {
-  // The longest strip that still gives every SIMD about two one-wave
-  // workgroups (float64: one and a half): long strips recompute fewer of
-  // the 6 halo rows (measured on MI355X: 4096^2 -> 64-128 rows).
+  // Before the device is known (buffer sizing): the longest strip that still
+  // gives every SIMD about two one-wave workgroups (float64: one and a half);
+  // lbm_create replaces it by round_tile_y for the device of the buffer.
   if (small_lattice(nx, ny, walls)) return std::max(2, std::min(5, std::max(ny, 2)));
   const int ntx = (nx + tile_x(walls) - 1) / tile_x(walls);
   const int want = fp32 ? 2048 : 1536;
@@ -47,6 +47,19 @@ int default_tile_y(int nx, int ny, int walls, int fp32) {
     }
   }
   return std::max(2, std::min(ty, std::max(ny, 2)));
+}
+
+// Default strip height once the device is known: the smallest height whose
+// launch of one-wave workgroups fits in `per_simd` waves on each SIMD (4 per
+// compute unit).  A launch a few waves over a whole round leaves some SIMDs
+// one wave more than the rest, and they set its time.  3 waves per SIMD for
+// float32 storage and 2 for float64 were the measured optima on MI355X (4096^2
+// pool: 100 / 152 rows; 1024 x 2048 pool: 13 / 20 rows).
+int round_tile_y(int ntx, int ny, int cus, int per_simd) {
+  const int hi = std::max(ny, 2);
+  const long long strips = static_cast<long long>(per_simd) * 4 * cus / ntx;
+  if (strips < 1) return hi;
+  return static_cast<int>(std::min<long long>(hi, std::max<long long>(2, (ny + strips - 1) / strips)));
 }
 
 int strip_waves(const lbm_ctx* c) {
@@ -234,6 +247,19 @@ lbm_status lbm_create(const lbm_params* p, void* dev_buf, size_t bytes, void* hi
   if (!c) return fail(nullptr, LBM_E_NOMEM, "host allocation failed");
   c->p = *p;
   c->L = L;
+  if (p->tile_y <= 0 && !small_lattice(p->nx, p->ny, p->walls)) {
+    hipPointerAttribute_t attr;
+    int cus = 0;
+    if (hipPointerGetAttributes(&attr, dev_buf) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, attr.device) == hipSuccess &&
+        cus > 0) {
+      c->L.ty = round_tile_y(L.ntx, p->ny, cus, p->precision == LBM_FP32_SHIFTED ? 3 : 2);
+      c->L.nty = (p->ny + c->L.ty - 1) / c->L.ty;
+      c->L.nblocks = c->L.ntx * c->L.nty;
+    } else {
+      (void)hipGetLastError();  // keep the device-independent default
+    }
+  }
   c->ph = make_phys(*p);
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->base = static_cast<char*>(dev_buf);

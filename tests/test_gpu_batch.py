@@ -153,6 +153,14 @@ def test_tile_candidates_fill_whole_rounds():
         rounds = {m for m in range(1, 17) if m * slots >= 11 * w}
         assert len(got) <= len(rounds)
     assert lat.tile_candidates(0) == lat.tile_candidates(lat.strip_waves)
+    # the default strip height of a lattice too large for the small-lattice
+    # rule: the smallest height that fits 2 (float64) / 3 (float32) waves per SIMD
+    for precision, per_simd in ((0, 2), (1, 3)):
+        big = _make(_pool_case(1200, 1000, 4, gy=0.0), precision=precision)  # 22 column tiles
+        ty = big.tile_y
+        print(f"precision {precision}: default tile_y {ty}", flush=True)
+        assert big.strip_waves == 1 and ty in big.tile_candidates(1)
+        assert 22 * (-(-1000 // ty)) <= per_simd * slots < 22 * (-(-1000 // (ty - 1)))
 
 
 def test_droplet_refinement_converges():
