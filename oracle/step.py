@@ -208,9 +208,11 @@ class Sim:
         d = self.tkind == DIRICHLET
         T[d] = self.tval[d]
         ab = self.tkind[0, :] == ADIABATIC
-        T[0, ab] = T[1, ab]
+        if ab.any():  # (a lattice of one row has no row above its bottom row)
+            T[0, ab] = T[1, ab]
         at = self.tkind[ny - 1, :] == ADIABATIC
-        T[ny - 1, at] = T[ny - 2, at]
+        if at.any():
+            T[ny - 1, at] = T[ny - 2, at]
         return T
 
     def init_fields(self, rho, ux=None, uy=None, T=None):

@@ -71,6 +71,25 @@ def test_one_step_random_state(nx, ny, walls, thermal, gy, waves):
     _compare(lat, s, 1e-11, "step5")
 
 
+@pytest.mark.parametrize("nx,ny,waves", [(1, 1, 1), (2, 2, 1), (1, 6, 1), (6, 1, 1), (3, 2, 2),
+                                          (1, 6, 2), (6, 1, 2)])
+def test_one_step_degenerate_periodic(nx, ny, waves):
+    """Periodic lattices narrower than the stencils (every neighbour wraps
+    onto the node itself or onto its one neighbour), energy equation on."""
+    print(f"case degenerate nx={nx} ny={ny} waves={waves}", flush=True)
+    c, rho, ux, uy, T = cases.random_tiny(nx, ny, seed=nx * 100 + ny + 7, thermal=True)
+    s = _oracle(c, rho, ux, uy, T)
+    lat = _lat(c, strip_waves=waves)
+    lat.init_fields(rho, ux, uy, T)
+    _compare(lat, s, 1e-13, "init")
+    s.step(1)
+    lat.step(1)
+    _compare(lat, s, 1e-12, "step1")
+    s.step(4)
+    lat.step(4)
+    _compare(lat, s, 1e-11, "step5")
+
+
 @pytest.mark.parametrize("nx,ny,thermal,gy,waves", [
     (7, 8, True, 0.0, 1),
     (9, 7, True, -2e-3, 1),

@@ -36,6 +36,45 @@ def test_uniform_state_is_a_fixed_point():
         assert np.all(s.T == T86)
 
 
+def test_single_node_relaxes_each_moment_geometrically():
+    """On a 1 x 1 periodic lattice every neighbour is the node itself: no
+    force, no Q, streaming is the identity and the conduction and dilatation
+    terms vanish, so a step is bare MRT relaxation.  Each non-conserved
+    Lallemand-Luo moment (written out here from the velocities) approaches
+    its equilibrium by the factor 1 - s_k per step; rho, j and T stay put."""
+    rng = np.random.default_rng(11)
+    p = Params(nx=1, ny=1, a=A, sigma=0.11, kappa=0.3, s_rho=1.0, s_e=0.8, s_zeta=0.9, s_j=1.1,
+               s_q=1.3, eta_l=0.15, eta_v=0.07, rho_l=RL, rho_v=RV, thermal=True, cv=5.0)
+    s = Sim(p)
+    one = np.ones((1, 1))
+    s.init_fields(2.3 * one, 0.01 * one, -0.02 * one, T=T86 * one)
+    s.f = s.f * (1.0 + 0.05 * rng.standard_normal(s.f.shape))
+    cx = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], dtype=float)
+    cy = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], dtype=float)
+    c2 = cx * cx + cy * cy
+    basis = {"e": -4 + 3 * c2, "eps": 4 - 10.5 * c2 + 4.5 * c2 * c2, "qx": (-5 + 3 * c2) * cx,
+             "qy": (-5 + 3 * c2) * cy, "pxx": cx * cx - cy * cy, "pxy": cx * cy}
+
+    def moments(f):
+        f = f[:, 0, 0]
+        return f.sum(), (f * cx).sum(), (f * cy).sum(), {k: (v * f).sum() for k, v in basis.items()}
+
+    rho, jx, jy, m0 = moments(s.f)
+    j2 = jx * jx + jy * jy
+    eq = {"e": -2 * rho + 3 * j2 / rho, "eps": rho - 3 * j2 / rho, "qx": -jx, "qy": -jy,
+          "pxx": (jx * jx - jy * jy) / rho, "pxy": jx * jy / rho}
+    eta = 0.07 + (0.15 - 0.07) * (rho - RV) / (RL - RV)
+    snu = 1.0 / (3.0 * eta + 0.5)
+    rate = {"e": 0.8, "eps": 0.9, "qx": 1.3, "qy": 1.3, "pxx": snu, "pxy": snu}
+    for n in range(1, 6):
+        s.step(1)
+        r, ax, ay, m = moments(s.f)
+        np.testing.assert_allclose([r, ax, ay], [rho, jx, jy], rtol=0, atol=1e-14)
+        for k in basis:
+            assert abs((m[k] - eq[k]) - (1 - rate[k]) ** n * (m0[k] - eq[k])) < 1e-13, (n, k)
+        assert abs(s.T[0, 0] - T86) < 1e-16
+
+
 @pytest.mark.parametrize("walls", [False, True])
 def test_collision_conserves_mass_and_adds_force(walls):
     rng = np.random.default_rng(7)
