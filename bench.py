@@ -630,7 +630,8 @@ def main():
         if args.only not in (name, "both"):
             continue
         log(f"bench: {name} {nx}x{ny} vaporisation, warmup {args.warmup}, steps {args.steps}")
-        res[name] = run_lattice(case, prec, args.warmup, args.steps, tile_y=args.tile_y, tune=tune)
+        res[name] = run_lattice(case, prec, args.warmup, args.steps, tile_y=args.tile_y, tune=tune,
+                                strip_waves=args.strip_waves)
         r = res[name]
         log(f"bench: {name} {args.steps * nodes / r['wall_s'] / 1e6:.0f} MLUPS, kernel "
             f"{r['kernel_ms_avg'] * 1e3:.2f} us avg over {r['launches']} launches, "
