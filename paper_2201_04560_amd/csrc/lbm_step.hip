@@ -327,6 +327,17 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
     val = 0.0;
     return int(T_FREE);
   };
+  // the same as a select (no divergent branch), for the two-wave march
+  auto node_kind_sel = [&](int y, double& val) {
+    int k = T_FREE;
+    val = 0.0;
+    if (y == 0 || y == ny - 1) k = row_kind(y, 1, val);  // uniform over the wave
+    if (side_col) {
+      val = P.t_side_val;
+      k = T_DIRICHLET;
+    }
+    return k;
+  };
 
   // ------------------------------------------------------------ stage A(r)
   // moments, EOS and psi of row r (slot SA); wall rows keep the known part
@@ -619,120 +630,159 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
   };
 
   // ------------------------------------------------------------ stage C(c)
-  // RK2 stage temperature T* of row c (slot SC)
-  auto stageC = [&](auto scc, const int c, const C a1, const C a2, const C irho, EnergyCoef<C>& ec_out) {
+  // RK2 stage temperature T* of a free node of the row in slot kc (rows in
+  // slots km, kc, kq); fills the energy coefficients that stage D reuses
+  auto stageC_core = [&](const int km, const int kc, const int kq, const C a1, const C a2,
+                         const C irho, EnergyCoef<C>& ec) {
+    const int kr[3] = {km, kc, kq};
+    C phi[3][3], rr[3][3], uxn[3][3], uyn[3][3];
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) {
+      const int sr = kr[dy];
+      phi[dy][0] = s_T[sr][lm];
+      phi[dy][1] = s_T[sr][lane];
+      phi[dy][2] = s_T[sr][lp];
+      if constexpr (kRhoC) {
+        rr[dy][0] = s_rc[sr][lm];
+        rr[dy][1] = s_rc[sr][lane];
+        rr[dy][2] = s_rc[sr][lp];
+      } else {
+        rr[dy][0] = C(s_rho[sr][lm]);
+        rr[dy][1] = C(s_rho[sr][lane]);
+        rr[dy][2] = C(s_rho[sr][lp]);
+      }
+      uxn[dy][0] = s_ux[sr][lm];
+      uxn[dy][1] = s_ux[sr][lane];
+      uxn[dy][2] = s_ux[sr][lp];
+      uyn[dy][0] = s_uy[sr][lm];
+      uyn[dy][1] = s_uy[sr][lane];
+      uyn[dy][2] = s_uy[sr][lp];
+    }
+    const C inv_rcv = irho * Q.inv_cv;
+    const C lam0 = Q.lambda_v + Q.dlam * (rr[1][1] - Q.rho_v);
+    ec.ux = uxn[1][1];
+    ec.uy = uyn[1][1];
+    ec.divu = gradx9(uxn) + grady9(uyn);
+    ec.glx = Q.dlam * gradx9(rr);
+    ec.gly = Q.dlam * grady9(rr);
+    ec.lam_rcv = lam0 * inv_rcv;
+    ec.inv_rcv = inv_rcv;
+    const C dpdt_n = dpdt_at(a1, a2, phi[1][1], Q);
+    const C Ts = phi[1][1] + C(0.5) * energy_rhs(phi, ec, dpdt_n);
+    ec.dpdt_s = dpdt_at(a1, a2, Ts, Q);
+    return Ts;
+  };
+  // stage C of row c (slot SC).  SEL (two-wave march): the free-node update
+  // is evaluated on every lane and kept by a select, with no divergent
+  // branch (512^2: float32 15.1 -> 14.2 us, float64 17.6 -> 16.6 us per step
+  // on MI355X; in the one-wave march the select measured up to 2 % slower
+  // on the 4096^2 pool, so it branches)
+  auto stageC = [&](auto scc, auto selc, const int c, const C a1, const C a2, const C irho,
+                    EnergyCoef<C>& ec_out) {
+    constexpr bool SEL = decltype(selc)::value;
     const int SC = int(scc);
     const int km = (SC + R - 1) & (R - 1), kc = SC, kq = (SC + 1) & (R - 1);
     const bool have = WALLS ? (c >= 0 && c < ny) : true;
     if (!have) return;
     const int yc = WALLS ? c : wrap3(c, ny);
     double tval;
-    const int kind = node_kind(yc, tval);
-    C Ts;
-    if (kind == T_FREE) {
-      const int kr[3] = {km, kc, kq};
-      C phi[3][3], rr[3][3], uxn[3][3], uyn[3][3];
-#pragma unroll
-      for (int dy = 0; dy < 3; ++dy) {
-        const int sr = kr[dy];
-        phi[dy][0] = s_T[sr][lm];
-        phi[dy][1] = s_T[sr][lane];
-        phi[dy][2] = s_T[sr][lp];
-        if constexpr (kRhoC) {
-          rr[dy][0] = s_rc[sr][lm];
-          rr[dy][1] = s_rc[sr][lane];
-          rr[dy][2] = s_rc[sr][lp];
-        } else {
-          rr[dy][0] = C(s_rho[sr][lm]);
-          rr[dy][1] = C(s_rho[sr][lane]);
-          rr[dy][2] = C(s_rho[sr][lp]);
-        }
-        uxn[dy][0] = s_ux[sr][lm];
-        uxn[dy][1] = s_ux[sr][lane];
-        uxn[dy][2] = s_ux[sr][lp];
-        uyn[dy][0] = s_uy[sr][lm];
-        uyn[dy][1] = s_uy[sr][lane];
-        uyn[dy][2] = s_uy[sr][lp];
-      }
+    // ADIABATIC rows get tval here and are substituted by the reader
+    if constexpr (SEL) {
+      const int kind = node_kind_sel(yc, tval);
       EnergyCoef<C> ec;
-      const C inv_rcv = irho * Q.inv_cv;
-      const C lam0 = Q.lambda_v + Q.dlam * (rr[1][1] - Q.rho_v);
-      ec.ux = uxn[1][1];
-      ec.uy = uyn[1][1];
-      ec.divu = gradx9(uxn) + grady9(uyn);
-      ec.glx = Q.dlam * gradx9(rr);
-      ec.gly = Q.dlam * grady9(rr);
-      ec.lam_rcv = lam0 * inv_rcv;
-      ec.inv_rcv = inv_rcv;
-      const C dpdt_n = dpdt_at(a1, a2, phi[1][1], Q);
-      Ts = phi[1][1] + C(0.5) * energy_rhs(phi, ec, dpdt_n);
-      ec.dpdt_s = dpdt_at(a1, a2, Ts, Q);
+      const C Tf = stageC_core(km, kc, kq, a1, a2, irho, ec);
       ec_out = ec;
+      s_Ts[kc][lane] = kind == T_FREE ? Tf : C(tval);
     } else {
-      Ts = C(tval);  // ADIABATIC rows are substituted by the reader
+      const int kind = node_kind(yc, tval);
+      C Ts;
+      if (kind == T_FREE) {
+        EnergyCoef<C> ec;
+        Ts = stageC_core(km, kc, kq, a1, a2, irho, ec);
+        ec_out = ec;
+      } else {
+        Ts = C(tval);
+      }
+      s_Ts[kc][lane] = Ts;
     }
-    s_Ts[kc][lane] = Ts;
   };
 
   // ------------------------------------------------------------ stage D(d)
-  // new temperature of row d (slot SD), d inside the strip
-  auto stageD = [&](auto sdc, const int d, const EnergyCoef<C>& ec) {
+  // new temperature of a free node of the row in slot kc (row index yd)
+  auto stageD_core = [&](const int km, const int kc, const int kq, const int yd,
+                         const EnergyCoef<C>& ec) {
+    C phi[3][3];
+    phi[0][0] = s_Ts[km][lm];
+    phi[0][1] = s_Ts[km][lane];
+    phi[0][2] = s_Ts[km][lp];
+    phi[1][0] = s_Ts[kc][lm];
+    phi[1][1] = s_Ts[kc][lane];
+    phi[1][2] = s_Ts[kc][lp];
+    phi[2][0] = s_Ts[kq][lm];
+    phi[2][1] = s_Ts[kq][lane];
+    phi[2][2] = s_Ts[kq][lp];
+    // adiabatic rows 0 / ny-1 take the stage value of their neighbour row
+    if (yd == 1) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        double tv;
+        if (row_kind(0, j, tv) == T_ADIABATIC) phi[0][j] = phi[1][j];
+      }
+    }
+    if (yd == ny - 2) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        double tv;
+        if (row_kind(ny - 1, j, tv) == T_ADIABATIC) phi[2][j] = phi[1][j];
+      }
+    }
+    const C T0 = s_T[kc][lane];
+    return T0 + energy_rhs(phi, ec, ec.dpdt_s);
+  };
+  // store of a node's new temperature (deferred or not)
+  auto store_T = [&](char* trow, const int yd, const S v) {
+    if constexpr (DEFER) {
+      dq_T = v;
+      dq_Ton = true;
+      dq_Trow = yd;
+    } else {
+      st(trow, ox, v);
+    }
+  };
+  // adiabatic boundary rows copy the new value of their neighbour row
+  auto adiabatic_copies = [&](const int yd, const S v) {
+    double tv;
+    if (yd == 1 && row_kind(0, 1, tv) == T_ADIABATIC) st(Tout, ox, v);
+    if (yd == ny - 2 && row_kind(ny - 1, 1, tv) == T_ADIABATIC)
+      st(Tout + size_t(ny - 1) * row_b, ox, v);
+  };
+  // stage D of row d (slot SD), d inside the strip; SEL as in stage C.
+  // DIRICHLET nodes store their value, ADIABATIC ones nothing.
+  auto stageD = [&](auto sdc, auto selc, const int d, const EnergyCoef<C>& ec) {
+    constexpr bool SEL = decltype(selc)::value;
     const int SD = int(sdc);
     const int km = (SD + R - 1) & (R - 1), kc = SD, kq = (SD + 1) & (R - 1);
     const int yd = d;
-    double tval;
-    const int kind = node_kind(yd, tval);
     char* trow = Tout + size_t(__builtin_amdgcn_readfirstlane(yd)) * row_b;
-    if (kind == T_FREE) {
-      C phi[3][3];
-      phi[0][0] = s_Ts[km][lm];
-      phi[0][1] = s_Ts[km][lane];
-      phi[0][2] = s_Ts[km][lp];
-      phi[1][0] = s_Ts[kc][lm];
-      phi[1][1] = s_Ts[kc][lane];
-      phi[1][2] = s_Ts[kc][lp];
-      phi[2][0] = s_Ts[kq][lm];
-      phi[2][1] = s_Ts[kq][lane];
-      phi[2][2] = s_Ts[kq][lp];
-      // adiabatic rows 0 / ny-1 take the stage value of their neighbour row
-      if (yd == 1) {
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          double tv;
-          if (row_kind(0, j, tv) == T_ADIABATIC) phi[0][j] = phi[1][j];
-        }
+    double tval;
+    if constexpr (SEL) {
+      const int kind = node_kind_sel(yd, tval);
+      const bool fr = kind == T_FREE;
+      const C Tnew = stageD_core(km, kc, kq, yd, ec);
+      if (outlane && kind != T_ADIABATIC) {
+        store_T(trow, yd, fr ? S(Tnew) : S(tval));
+        if (fr) adiabatic_copies(yd, S(Tnew));
       }
-      if (yd == ny - 2) {
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          double tv;
-          if (row_kind(ny - 1, j, tv) == T_ADIABATIC) phi[2][j] = phi[1][j];
+    } else {
+      const int kind = node_kind(yd, tval);
+      if (kind == T_FREE) {
+        const C Tnew = stageD_core(km, kc, kq, yd, ec);
+        if (outlane) {
+          store_T(trow, yd, S(Tnew));
+          adiabatic_copies(yd, S(Tnew));
         }
-      }
-      const C T0 = s_T[kc][lane];
-      const C Tnew = T0 + energy_rhs(phi, ec, ec.dpdt_s);
-      if (outlane) {
-        if constexpr (DEFER) {
-          dq_T = S(Tnew);
-          dq_Ton = true;
-          dq_Trow = yd;
-        } else {
-          st(trow, ox, S(Tnew));
-        }
-        double tv;
-        if (yd == 1 && row_kind(0, 1, tv) == T_ADIABATIC) st(Tout, ox, S(Tnew));
-        if (yd == ny - 2 && row_kind(ny - 1, 1, tv) == T_ADIABATIC)
-          st(Tout + size_t(ny - 1) * row_b, ox, S(Tnew));
-      }
-    } else if (kind == T_DIRICHLET) {
-      if (outlane) {
-        if constexpr (DEFER) {
-          dq_T = S(tval);
-          dq_Ton = true;
-          dq_Trow = yd;
-        } else {
-          st(trow, ox, S(tval));
-        }
+      } else if (kind == T_DIRICHLET) {
+        if (outlane) store_T(trow, yd, S(tval));
       }
     }
   };
@@ -801,14 +851,16 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
         // EOS terms of row c: stage A two rows back; 1/rho: stage B one row back
         const C a1 = a1h[RPI == 2 ? j : 0], a2 = a2h[RPI == 2 ? j : 0];
         const C ir = j == 0 ? irprev : irc[j > 0 ? j - 1 : 0];
-        if (c >= rbase + 2 && c <= rend - 3) stageC(Ph<SC>{}, c, a1, a2, ir, ecc[j]);
+        if (c >= rbase + 2 && c <= rend - 3)
+          stageC(Ph<SC>{}, std::false_type{}, c, a1, a2, ir, ecc[j]);
       });
       stage_barrier();
       static_for<RPI>([&](auto jc) {
         constexpr int j = decltype(jc)::value;
         constexpr int SD = (RPI * PH + j + R - 3) & (R - 1);
         const int d = r0 + j - 3;
-        if (d >= y0 && d < y1) stageD(Ph<SD>{}, d, j == 0 ? ecprev : ecc[j > 0 ? j - 1 : 0]);
+        if (d >= y0 && d < y1)
+          stageD(Ph<SD>{}, std::false_type{}, d, j == 0 ? ecprev : ecc[j > 0 ? j - 1 : 0]);
       });
       stage_barrier();
     }
@@ -844,14 +896,18 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
     // iterations.  Ring slot of row q: (q - rbase) & 7; in iteration k wave
     // 0 writes rows r, r - 1 while wave 1 reads rows >= r - 5.
     const int niter = nit + 1;
+    // the loop is unrolled by the ring length, so that every ring slot is a
+    // constant (LDS addresses become immediate offsets; 16.0 -> 15.1 us per
+    // float32 step at 512^2 on MI355X, float64 18.6 -> 17.6 us)
     if (wave == 0) {
       // wave 0 carries the longer chain (pull, EOS, forces, collision): it
       // goes first when waves of its SIMD compete for an issue slot (float64
       // 512^2: 19.5 -> 18.6 us per step on MI355X; float32 unchanged)
       __builtin_amdgcn_s_setprio(2);
-      for (int k = 0; k < niter; ++k) {
+      auto w0 = [&](auto phc, const int k) {
+        constexpr int PH = decltype(phc)::value;
+        constexpr int SR = PH, SR1 = (PH + R - 1) & (R - 1);
         const int r = rbase + k;
-        const int sr = k & (R - 1), sr1 = (k + R - 1) & (R - 1);
         if (k < nit) {
           C g[9], jx, jy, a1, a2;
 #pragma unroll
@@ -862,20 +918,20 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
             flush_stores();
           }
           if (r + 1 < rend) load_row(r + 1, gn[0], Tn[0]);
-          stageA(sr, r, g, Tr, jx, jy, a1, a2);
-          s_a1[sr][lane] = a1;
-          s_a2[sr][lane] = a2;
+          stageA(Ph<SR>{}, r, g, Tr, jx, jy, a1, a2);
+          s_a1[SR][lane] = a1;
+          s_a2[SR][lane] = a2;
           stage_barrier();
           if (WALLS) {
-            if (r == 1 && 0 >= rbase) closure(sr1, sr, true);
-            if (r == ny - 1 && ny - 2 >= rbase && !outflow) closure(sr, sr1, false);
+            if (r == 1 && 0 >= rbase) closure(Ph<SR1>{}, Ph<SR>{}, true);
+            if (r == ny - 1 && ny - 2 >= rbase && !outflow) closure(Ph<SR>{}, Ph<SR1>{}, false);
             stage_barrier();
           }
           const int sB = r - 1;
           if (sB >= rbase + 1 && sB <= rend - 2) {
             C ir = C(0);
-            stageB(sr1, sB, gprev, jxprev, jyprev, ir);
-            s_ir[sr1][lane] = ir;
+            stageB(Ph<SR1>{}, sB, gprev, jxprev, jyprev, ir);
+            s_ir[SR1][lane] = ir;
           }
 #pragma unroll
           for (int i = 0; i < 9; ++i) gprev[i] = g[i];
@@ -883,21 +939,41 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
           jyprev = jy;
         }
         __syncthreads();
+      };
+      for (int kb = 0; kb < niter; kb += 8) {
+        w0(Ph<0>{}, kb);
+        if (kb + 1 < niter) w0(Ph<1>{}, kb + 1);
+        if (kb + 2 < niter) w0(Ph<2>{}, kb + 2);
+        if (kb + 3 < niter) w0(Ph<3>{}, kb + 3);
+        if (kb + 4 < niter) w0(Ph<4>{}, kb + 4);
+        if (kb + 5 < niter) w0(Ph<5>{}, kb + 5);
+        if (kb + 6 < niter) w0(Ph<6>{}, kb + 6);
+        if (kb + 7 < niter) w0(Ph<7>{}, kb + 7);
       }
     } else {
       EnergyCoef<C> ecw{};
-      for (int k = 0; k < niter; ++k) {
+      auto w1 = [&](auto phc, const int k) {
+        constexpr int PH = decltype(phc)::value;
+        constexpr int SC = (PH + R - 3) & (R - 1), SD = (PH + R - 4) & (R - 1);
         const int r = rbase + k;
         const int c = r - 3, d = r - 4;
         EnergyCoef<C> ecn{};
-        if (c >= rbase + 2 && c <= rend - 3) {
-          const int sc = (k + R - 3) & (R - 1);
-          stageC(sc, c, s_a1[sc][lane], s_a2[sc][lane], s_ir[sc][lane], ecn);
-        }
+        if (c >= rbase + 2 && c <= rend - 3)
+          stageC(Ph<SC>{}, std::true_type{}, c, s_a1[SC][lane], s_a2[SC][lane], s_ir[SC][lane], ecn);
         stage_barrier();
-        if (d >= y0 && d < y1) stageD((k + R - 4) & (R - 1), d, ecw);
+        if (d >= y0 && d < y1) stageD(Ph<SD>{}, std::true_type{}, d, ecw);
         ecw = ecn;
         __syncthreads();
+      };
+      for (int kb = 0; kb < niter; kb += 8) {
+        w1(Ph<0>{}, kb);
+        if (kb + 1 < niter) w1(Ph<1>{}, kb + 1);
+        if (kb + 2 < niter) w1(Ph<2>{}, kb + 2);
+        if (kb + 3 < niter) w1(Ph<3>{}, kb + 3);
+        if (kb + 4 < niter) w1(Ph<4>{}, kb + 4);
+        if (kb + 5 < niter) w1(Ph<5>{}, kb + 5);
+        if (kb + 6 < niter) w1(Ph<6>{}, kb + 6);
+        if (kb + 7 < niter) w1(Ph<7>{}, kb + 7);
       }
     }
   }
