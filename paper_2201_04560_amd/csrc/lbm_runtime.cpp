@@ -63,8 +63,12 @@ int round_tile_y(int ntx, int ny, int cus, int per_simd) {
 }
 
 int strip_waves(const lbm_ctx* c) {
-  if (c->p.strip_waves == 1 || c->p.strip_waves == 2) return c->p.strip_waves;
-  return small_lattice(c->p.nx, c->p.ny, c->p.walls) ? 2 : 1;
+  int w = (c->p.strip_waves == 1 || c->p.strip_waves == 2)
+              ? c->p.strip_waves
+              : (small_lattice(c->p.nx, c->p.ny, c->p.walls) ? 2 : 1);
+  // the two-wave march addresses the 9 population planes with 32-bit offsets
+  if (w == 2 && two_wave_fits(c->L.plane, c->L.elem) == 0) w = 1;
+  return w;
 }
 
 }  // namespace

@@ -163,6 +163,27 @@ def test_tile_candidates_fill_whole_rounds():
         assert 22 * (-(-1000 // ty)) <= per_simd * slots < 22 * (-(-1000 // (ty - 1)))
 
 
+def test_two_waves_only_below_4gib_of_planes():
+    """The two-wave march addresses the 9 population planes with 32-bit
+    offsets: a lattice whose planes span 4 GiB or more runs one wave even
+    when two are asked for (no fields are initialised: nothing runs)."""
+    print("case strip waves 4 GiB", flush=True)
+    from paper_2201_04560_amd import LBM_FP64, Lattice, make_params
+
+    small = Lattice(make_params(64, 48, precision=LBM_FP64, thermal=1))
+    small.strip_waves = 2
+    assert small.strip_waves == 2
+    small.close()
+    big = Lattice(make_params(8192, 7300, precision=LBM_FP64, thermal=1))  # 9 x 478 MB planes
+    big.strip_waves = 2
+    assert big.strip_waves == 1
+    big.close()
+    del big
+    import torch
+
+    torch.cuda.empty_cache()
+
+
 def test_droplet_refinement_converges():
     """Sec. 4.1 refinement on three meshes (64, 96, 144; a, sigma, kappa by
     the Sec. 3 rules, Delta t ~ Delta x^2) in one batch: the droplet radius
