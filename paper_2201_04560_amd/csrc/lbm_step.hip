@@ -221,6 +221,14 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
                           oxm + 5 * pb32, oxp + 6 * pb32, oxp + 7 * pb32, oxm + 8 * pb32};
   const uint32_t so[9] = {ox,           ox + pb32,     ox + 2 * pb32, ox + 3 * pb32, ox + 4 * pb32,
                           ox + 5 * pb32, ox + 6 * pb32, ox + 7 * pb32, ox + 8 * pb32};
+  // byte offset of row y >= 0 (OFF32: one 32-bit multiply)
+  const uint32_t rb32 = uint32_t(row_b);
+  auto roff = [&](const int y) -> size_t {
+    if constexpr (OFF32)
+      return size_t(uint32_t(y) * rb32);
+    else
+      return size_t(y) * row_b;
+  };
 
   // rings of R rows indexed by (row - first row) & (R - 1)
   constexpr int R = WS ? 8 : 4 * RPI;  // ring rows
@@ -267,9 +275,9 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
       ydn = (yr == 0) ? ny - 1 : yr - 1;
       yup = (yr == ny - 1) ? 0 : yr + 1;
     }
-    const char* rc = fin + size_t(yr) * row_b;
-    const char* rd = fin + size_t(ydn) * row_b;
-    const char* ru = fin + size_t(yup) * row_b;
+    const char* rc = fin + roff(yr);
+    const char* rd = fin + roff(ydn);
+    const char* ru = fin + roff(yup);
     C v2, v5, v6, v4, v7, v8;
     if constexpr (OFF32) {
       gn[0] = C(ld(rc, lo[0]));
@@ -301,7 +309,7 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
     gn[4] = kin ? v4 : C(0);
     gn[7] = kin ? v7 : C(0);
     gn[8] = kin ? v8 : C(0);
-    Tn = C(ld(Tin + size_t(yr) * row_b, ox));
+    Tn = C(ld(Tin + roff(yr), ox));
   };
 
   uint32_t err = 0;
@@ -513,7 +521,7 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
       dq_fon = true;
       dq_frow = ys;
     } else {
-      char* orow = fout + size_t(__builtin_amdgcn_readfirstlane(ys)) * row_b;
+      char* orow = fout + roff(__builtin_amdgcn_readfirstlane(ys));
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         if constexpr (OFF32)
@@ -794,7 +802,7 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
     const int SD = int(sdc);
     const int km = (SD + R - 1) & (R - 1), kc = SD, kq = (SD + 1) & (R - 1);
     const int yd = d;
-    char* trow = Tout + size_t(__builtin_amdgcn_readfirstlane(yd)) * row_b;
+    char* trow = Tout + roff(__builtin_amdgcn_readfirstlane(yd));
     double tval;
     if constexpr (SEL) {
       const int kind = node_kind_sel(yd, tval);
