@@ -180,7 +180,8 @@ int32_t lbm_get_tile_y(const lbm_ctx* ctx);
 /* Waves marching each strip in the energy step: 1 (one wave, all stages),
  * 2 (a second wave takes the RK2 stages one row behind), 0 = by lattice
  * size.  Identical results; a performance choice.  2 applies while the 9
- * population planes span less than 4 GiB (larger lattices run one wave).
+ * population planes span less than 4 GiB and ny >= 3 (other lattices run
+ * one wave).
  * get returns the effective value. */
 lbm_status lbm_set_strip_waves(lbm_ctx* ctx, int32_t waves);
 int32_t lbm_get_strip_waves(const lbm_ctx* ctx);

@@ -11,9 +11,10 @@ namespace lbm {
 constexpr int kNormSlots = 9;
 
 // The two-wave march addresses a row's 9 population planes with 32-bit
-// per-lane byte offsets: usable while the 9 planes span less than 4 GiB.
-inline bool two_wave_fits(long long plane, int elem) {
-  return 9ll * plane * elem < (1ll << 32);
+// per-lane byte offsets, usable while the 9 planes span less than 4 GiB, and
+// wraps periodic rows with one correction, which needs ny >= 3.
+inline bool two_wave_fits(long long plane, int elem, int ny) {
+  return 9ll * plane * elem < (1ll << 32) && ny >= 3;
 }
 
 struct LaunchStep {

@@ -66,8 +66,8 @@ int strip_waves(const lbm_ctx* c) {
   int w = (c->p.strip_waves == 1 || c->p.strip_waves == 2)
               ? c->p.strip_waves
               : (small_lattice(c->p.nx, c->p.ny, c->p.walls) ? 2 : 1);
-  // the two-wave march addresses the 9 population planes with 32-bit offsets
-  if (w == 2 && two_wave_fits(c->L.plane, c->L.elem) == 0) w = 1;
+  // the two-wave march needs 9 population planes below 4 GiB and ny >= 3
+  if (w == 2 && !two_wave_fits(c->L.plane, c->L.elem, c->p.ny)) w = 1;
   return w;
 }
 

@@ -165,8 +165,9 @@ def test_tile_candidates_fill_whole_rounds():
 
 def test_two_waves_only_below_4gib_of_planes():
     """The two-wave march addresses the 9 population planes with 32-bit
-    offsets: a lattice whose planes span 4 GiB or more runs one wave even
-    when two are asked for (no fields are initialised: nothing runs)."""
+    offsets and wraps rows with one correction: a lattice whose planes span
+    4 GiB or more, or with fewer than 3 rows, runs one wave even when two
+    are asked for (no fields are initialised: nothing runs)."""
     print("case strip waves 4 GiB", flush=True)
     from paper_2201_04560_amd import LBM_FP64, Lattice, make_params
 
@@ -174,6 +175,10 @@ def test_two_waves_only_below_4gib_of_planes():
     small.strip_waves = 2
     assert small.strip_waves == 2
     small.close()
+    flat = Lattice(make_params(64, 2, precision=LBM_FP64, thermal=1))  # rows wrap more than once
+    flat.strip_waves = 2
+    assert flat.strip_waves == 1
+    flat.close()
     big = Lattice(make_params(8192, 7300, precision=LBM_FP64, thermal=1))  # 9 x 478 MB planes
     big.strip_waves = 2
     assert big.strip_waves == 1
