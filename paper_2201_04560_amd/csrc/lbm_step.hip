@@ -216,6 +216,11 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
   // wave's chain; 512^2 float32 14.3 -> 13.2 us on MI355X).  Needs 9 planes
   // below 4 GiB, which the launcher checks.
   constexpr bool OFF32 = WS;
+  // TRIM: wave 0 keeps its rows in a register ring and the loop is unrolled
+  // by the ring length (periodic lattices); with walls the unrolled closure
+  // code pushed the kernel into scratch memory, so there the loop keeps
+  // runtime ring slots and copies each row once
+  constexpr bool TRIM = WS && !WALLS;
   const uint32_t pb32 = uint32_t(plane_b);
   const uint32_t lo[9] = {ox,           oxm + pb32,     ox + 2 * pb32, oxp + 3 * pb32, ox + 4 * pb32,
                           oxm + 5 * pb32, oxp + 6 * pb32, oxp + 7 * pb32, oxm + 8 * pb32};
@@ -333,7 +338,7 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
     Tn[j] = C(0);
 #pragma unroll
     for (int i = 0; i < 9; ++i) gn[j][i] = C(0);
-    if (!WS && rbase + j < rend) load_row(rbase + j, gn[j], Tn[j]);
+    if (!TRIM && rbase + j < rend) load_row(rbase + j, gn[j], Tn[j]);
   }
   // two-wave march, wave 0: register ring of pulled rows, slot (row - rbase)
   // & 3 (a constant in the unrolled loop): row r is read from its slot, r + 1
@@ -341,14 +346,14 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
   // r does not wait for the new loads too) and r - 1 is still in the previous
   // one, so no row is copied between registers (with the one-correction row
   // wrap: 512^2 12.7 -> 12.3 us float32, 15.7 -> 15.2 us float64 on MI355X)
-  C gq[WS ? 4 : 1][9], Tq[WS ? 4 : 1];
+  C gq[TRIM ? 4 : 1][9], Tq[TRIM ? 4 : 1];
 #pragma unroll
-  for (int j = 0; j < (WS ? 4 : 1); ++j) {
+  for (int j = 0; j < (TRIM ? 4 : 1); ++j) {
     Tq[j] = C(0);
 #pragma unroll
     for (int i = 0; i < 9; ++i) gq[j][i] = C(0);
   }
-  if (WS && wave == 0 && rbase < rend) load_row(rbase, gq[0], Tq[0]);
+  if (TRIM && wave == 0 && rbase < rend) load_row(rbase, gq[0], Tq[0]);
   // carries from the previous iteration's last row (its pulled populations
   // and moments feed the next row's collision)
   C gprev[9];
@@ -960,7 +965,58 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
     // the loop is unrolled by the ring length, so that every ring slot is a
     // constant (LDS addresses become immediate offsets; 16.0 -> 15.1 us per
     // float32 step at 512^2 on MI355X, float64 18.6 -> 17.6 us)
-    if (wave == 0) {
+    if constexpr (!TRIM) {
+      // runtime ring slots (walls)
+      if (wave == 0) {
+        __builtin_amdgcn_s_setprio(2);
+        for (int k = 0; k < niter; ++k) {
+          const int r = rbase + k;
+          const int sr = k & (R - 1), sr1 = (k + R - 1) & (R - 1);
+          if (k < nit) {
+            C g[9], jx, jy, a1, a2;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) g[i] = gn[0][i];
+            const C Tr = Tn[0];
+            if (r + 1 < rend) load_row(r + 1, gn[0], Tn[0]);
+            stageA(sr, r, g, Tr, jx, jy, a1, a2);
+            s_a1[sr][lane] = a1;
+            s_a2[sr][lane] = a2;
+            stage_barrier();
+            if (WALLS) {
+              if (r == 1 && 0 >= rbase) closure(sr1, sr, true);
+              if (r == ny - 1 && ny - 2 >= rbase && !outflow) closure(sr, sr1, false);
+              stage_barrier();
+            }
+            const int sB = r - 1;
+            if (sB >= rbase + 1 && sB <= rend - 2) {
+              C ir = C(0);
+              stageB(sr1, sB, gprev, jxprev, jyprev, ir);
+              s_ir[sr1][lane] = ir;
+            }
+#pragma unroll
+            for (int i = 0; i < 9; ++i) gprev[i] = g[i];
+            jxprev = jx;
+            jyprev = jy;
+          }
+          __syncthreads();
+        }
+      } else {
+        EnergyCoef<C> ecw{};
+        for (int k = 0; k < niter; ++k) {
+          const int r = rbase + k;
+          const int c = r - 3, d = r - 4;
+          EnergyCoef<C> ecn{};
+          if (c >= rbase + 2 && c <= rend - 3) {
+            const int sc = (k + R - 3) & (R - 1);
+            stageC(sc, std::true_type{}, c, s_a1[sc][lane], s_a2[sc][lane], s_ir[sc][lane], ecn);
+          }
+          stage_barrier();
+          if (d >= y0 && d < y1) stageD((k + R - 4) & (R - 1), std::true_type{}, d, ecw);
+          ecw = ecn;
+          __syncthreads();
+        }
+      }
+    } else if (wave == 0) {
       // wave 0 carries the longer chain (pull, EOS, forces, collision): it
       // goes first when waves of its SIMD compete for an issue slot (float64
       // 512^2: 19.5 -> 18.6 us per step on MI355X; float32 unchanged)
