@@ -179,6 +179,9 @@ def write_traffic(pmc_dir, copy_mib):
             rows = list(csv.DictReader(fh))
         march = [float(r["Counter_Value"]) for r in rows if "lbm_march" in r["Kernel_Name"]]
         copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        if not march or not copies:
+            raise SystemExit(f"{f}: needs step-kernel dispatches and the calibration copy "
+                             "(run the profile case with --copy-mib > 0)")
         big = max(int(r["Grid_Size"]) for r in copies)
         cal = [float(r["Counter_Value"]) for r in copies if int(r["Grid_Size"]) == big]
         per.setdefault(case, {}).setdefault(cfg, {})[ctr] = dict(
