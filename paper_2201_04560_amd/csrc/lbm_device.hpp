@@ -108,25 +108,32 @@ __device__ __forceinline__ double dpsi_drho(double rho, double T, double psi, co
 // ------------------------------------------- fast float64 rcp / rsqrt / sqrt
 // Hardware estimates refined by two Newton steps: ~1 ulp, not correctly
 // rounded (the IEEE expansions cost 2-3x the instructions).
+// NR: Newton steps (2 by default; 1 where the result feeds float32 storage)
+template <int NR = 2>
 __device__ __forceinline__ double rcp64(double x) {
   double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
+#pragma unroll
+  for (int i = 0; i < NR; ++i) {
+    const double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+  }
+  return r;
 }
+template <int NR = 2>
 __device__ __forceinline__ double rsq64(double x) {
   double y = __builtin_amdgcn_rsq(x);
   const double h = 0.5 * x;
-  double t = fma(-h * y, y, 0.5);
-  y = fma(y, t, y);
-  t = fma(-h * y, y, 0.5);
-  return fma(y, t, y);
+#pragma unroll
+  for (int i = 0; i < NR; ++i) {
+    const double t = fma(-h * y, y, 0.5);
+    y = fma(y, t, y);
+  }
+  return y;
 }
 __device__ __forceinline__ float rsq_c(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double rsq_c(double x) { return rsq64(x); }
+__device__ __forceinline__ double rsq_c(double x) { return rsq64<2>(x); }
 __device__ __forceinline__ float rcp_c(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double rcp_c(double x) { return rcp64(x); }
+__device__ __forceinline__ double rcp_c(double x) { return rcp64<2>(x); }
 
 // EOS terms of one node, shared by psi (stage A) and (dp/dT)_rho (energy
 // stages): A1 = rho R / (1 - b rho), A2 = rho^2 / (1 + 2 b rho - b^2 rho^2),
@@ -134,27 +141,29 @@ __device__ __forceinline__ double rcp_c(double x) { return rcp64(x); }
 struct EosNode {
   double A1, A2, rsqT, rad;
 };
+template <int NR = 2>
 __device__ __forceinline__ EosNode eos_node(double rho, double T, const Phys& p) {
   EosNode e;
   const double br = p.b * rho;
   const double om = 1.0 - br;
   const double D = 1.0 + 2.0 * br - br * br;
-  const double inv = rcp64(om * D);
+  const double inv = rcp64<NR>(om * D);
   e.A1 = rho * p.R * D * inv;
   e.A2 = rho * rho * om * inv;
-  e.rsqT = rsq64(T);
+  e.rsqT = rsq64<NR>(T);
   const double sa = 1.0 + p.kw * (1.0 - T * e.rsqT * p.inv_sqrtTc);
   const double pr = e.A1 * T - p.a * (sa * sa) * e.A2;
   e.rad = (pr - rho * (1.0 / 3.0)) * p.two_G;
   return e;
 }
 // psi = sqrt(rad) with the domain checks of the method
+template <int NR = 2>
 __device__ __forceinline__ double psi_fast(double rho, double T, const EosNode& e, const Phys& p,
                                            uint32_t& err) {
   if (!(rho > 0.0) || !(rho < p.inv_b)) err |= ERR_RHO;
   if (!(T > 0.0)) err |= ERR_TEMP;
   if (!(e.rad > 0.0)) err |= ERR_RADICAND;
-  const double y = rsq64(e.rad);
+  const double y = rsq64<NR>(e.rad);
   double s = e.rad * y;  // one Newton correction of the root itself
   return fma(0.5 * y, fma(-s, s, e.rad), s);
 }

@@ -172,6 +172,9 @@ __device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70)
 template <class S, class C, int WM, bool THERMAL, int MODE, int RPI, bool WS>
 __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroOut& O, const int bid) {
   constexpr bool WALLS = WM != 0;
+  // Newton steps of the float64 reciprocals and square roots: one is below
+  // float32 storage's rounding by orders of magnitude
+  constexpr int kNR = sizeof(S) == 4 ? 1 : 2;
   constexpr bool WX = WM == 2;
   constexpr bool DEFER = kDeferStores && !WS && WALLS && sizeof(S) == 8;
   const bool wall_mod = WX && A.ph.wall_mod;
@@ -425,8 +428,8 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
         jx = g[1] - g[3] + g[5] - g[6] - g[7] + g[8];
         jy = g[2] - g[4] + g[5] + g[6] - g[7] - g[8];
         rho = rref + double(sg);
-        const EosNode e = eos_node(rho, T, P);
-        psi = psi_fast(rho, T, e, P, err);
+        const EosNode e = eos_node<kNR>(rho, T, P);
+        psi = psi_fast<kNR>(rho, T, e, P, err);
         a1 = C(e.A1);
         a2 = C(e.A2);
       }
@@ -651,7 +654,7 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
         gp[8] = gp[6] - d + C(0.5) * jxs - jys * C(1.0 / 6.0);
       }
     }
-    const double inv_rho = rcp64(rho);
+    const double inv_rho = rcp64<kNR>(rho);
     irho_out = C(inv_rho);
     const double uxd = (double(jxs) + 0.5 * fx) * inv_rho;
     const double uyd = (double(jys) + 0.5 * fy) * inv_rho;
@@ -673,7 +676,7 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
       ci[15] = C(rho);
       ci[16] = C(rho - rref);
       // sigma term 12 sigma |F^m|^2 / (psi^2 (tau - 1/2)) without the constant
-      ci[17] = C((fmx * fmx + fmy * fmy) * rcp64(pc * pc));
+      ci[17] = C((fmx * fmx + fmy * fmy) * rcp64<kNR>(pc * pc));
       ci[18] = C(qxx + qyy);
       ci[19] = C(qxx - qyy);
       ci[20] = C(qxy);
