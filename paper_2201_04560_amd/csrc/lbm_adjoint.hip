@@ -8,18 +8,19 @@
 //
 // Schedule.  The forward pass runs the fused step kernel and stores the
 // state (post-collision populations + T) every `ckpt` steps.  The backward
-// pass walks the segments last to first: it restores the segment's
-// checkpoint, re-runs the fused kernel over the segment keeping every state
-// (identical bits: same kernel, same tiling), then reverses the steps one by
-// one.  Each reversed step is a chain of plain float64 kernels, one node per
+// pass walks the segments last to first: it re-runs the fused kernel over
+// the segment from its checkpoint, each step writing straight into the
+// segment's next state slot (identical bits: same kernel, same tiling), then
+// reverses the steps one by one.  Each reversed step is a chain of plain float64 kernels, one node per
 // thread, each a local map or a radius-1 gather (the transposed stencil of a
 // forward scatter), so that no atomics are needed:
 //   fm1  rho, j, psi from the stored state (pull-stream)
 //   fm2  F^m, Q (kappa term), u
 //   fm3  the RK2 stage temperature T*
-//   per RK stage, second then first: mask (adjoint of the temperature
-//        boundary rule; Dirichlet bottom values accumulate into the
-//        gradient), coef (local partials of K), gather (transposed stencils)
+//   per RK stage, second then first: coef (the adjoint of the temperature
+//        boundary rule, whose Dirichlet bottom values accumulate into the
+//        gradient, then the local partials of K), gather (transposed
+//        stencils)
 //   ca   adjoint of the MRT collision with the forcing S and the C term,
 //        of u = (j + F/2)/rho and of the moments
 //   fa   adjoint of F^m and Q with respect to psi, then of psi(rho, T)
@@ -224,9 +225,9 @@ __global__ __launch_bounds__(kThreads) void k_fm3(Geo g, Phys ph, BC bc, Fields 
 // ------------------------------------------------------- energy adjoint
 // am = adjoint of the stage value before the boundary rule; Dirichlet
 // bottom entries (not the side columns) accumulate into grad
-__global__ __launch_bounds__(kThreads) void k_ea_mask(const double* __restrict__ gin, double* __restrict__ am,
-                                                      double* __restrict__ grad, Geo g, BC bc) {
-  NODE_LOOP;
+__device__ __forceinline__ double ea_mask(const double* __restrict__ gin, double* __restrict__ am,
+                                          double* __restrict__ grad, const Geo& g, const BC& bc, int id, int x,
+                                          int y) {
   const int k = kind_at(bc, x, y, g.nx, g.ny);
   double a = 0.0;
   if (k == T_DIRICHLET) {
@@ -237,18 +238,21 @@ __global__ __launch_bounds__(kThreads) void k_ea_mask(const double* __restrict__
     if (y == g.ny - 2 && kind_at(bc, x, g.ny - 1, g.nx, g.ny) == T_ADIABATIC) a += gin[(g.ny - 1) * g.nx + x];
   }
   am[id] = a;
+  return a;
 }
 
-// local partials of w * K(phi) at x, w = wfac * am(x)
+// the mask, then the local partials of w * K(phi) at x, w = wfac * am(x),
+// in one kernel (am is a local map of gin)
 template <bool FIRST>
-__global__ __launch_bounds__(kThreads) void k_ea_coef(const double* __restrict__ phi_arr,
-                                                      const double* __restrict__ am, double wfac, Geo g, Phys ph,
-                                                      Fields F) {
+__global__ __launch_bounds__(kThreads) void k_ea_coef(const double* __restrict__ gin, double* __restrict__ am,
+                                                      double* __restrict__ grad, BC bc,
+                                                      const double* __restrict__ phi_arr, double wfac, Geo g,
+                                                      Phys ph, Fields F) {
   NODE_LOOP;
   const double* rho = F.f[F_RHO];
   const double* ux = F.f[F_UX];
   const double* uy = F.f[F_UY];
-  const double w = wfac * am[id];
+  const double w = wfac * ea_mask(gin, am, grad, g, bc, id, x, y);
   const double p0 = phi_arr[id];
   double gx = 0, gy = 0, lap = 0, grx = 0, gry = 0, du = 0;
   for (int i = 1; i < 9; ++i) {
@@ -596,12 +600,12 @@ static hipError_t reverse_step(lbm_adjoint* a, const char* state, bool thermal_o
   if (thermal_on) {
     hipLaunchKernelGGL(k_fm3, grid, blk, 0, st, g, ph, a->bc, F);
     // stage 2: T' = BC(T + K(T*))
-    hipLaunchKernelGGL(k_ea_mask, grid, blk, 0, st, F.f[F_THAT], F.f[F_AM2], grad, g, a->bc);
-    hipLaunchKernelGGL(k_ea_coef<true>, grid, blk, 0, st, F.f[F_TS], F.f[F_AM2], 1.0, g, ph, F);
+    hipLaunchKernelGGL(k_ea_coef<true>, grid, blk, 0, st, F.f[F_THAT], F.f[F_AM2], grad, a->bc, F.f[F_TS], 1.0, g,
+                       ph, F);
     hipLaunchKernelGGL(k_ea_gather, grid, blk, 0, st, F.f[F_TSH], nullptr, nullptr, g, ph, F);
     // stage 1: T* = BC(T + K(T)/2)
-    hipLaunchKernelGGL(k_ea_mask, grid, blk, 0, st, F.f[F_TSH], F.f[F_AM1], grad, g, a->bc);
-    hipLaunchKernelGGL(k_ea_coef<false>, grid, blk, 0, st, F.f[F_T], F.f[F_AM1], 0.5, g, ph, F);
+    hipLaunchKernelGGL(k_ea_coef<false>, grid, blk, 0, st, F.f[F_TSH], F.f[F_AM1], grad, a->bc, F.f[F_T], 0.5, g,
+                       ph, F);
   }
   return hipGetLastError();
 }
@@ -718,6 +722,25 @@ static lbm_status adj_forward(lbm_adjoint* a, double* J) {
   return LBM_OK;
 }
 
+// one forward step of the fused kernel from the stored state `src` into the
+// slot `dst` (same layout as the context's buffers, same launch as lbm_step
+// at step index n, so the states are bit-identical to the forward run's);
+// without the energy update T is carried over
+static hipError_t step_into(lbm_adjoint* a, const char* src, char* dst, int64_t n) {
+  lbm_ctx* c = a->c;
+  LaunchStep L = step_args(c);
+  L.fin = src;
+  L.fout = dst;
+  L.Tin = src + al(a->fbytes);
+  L.Tout = dst + al(a->fbytes);
+  L.update_T = c->p.thermal && n >= c->p.n_iso;
+  L.want_mass = 0;
+  hipError_t e = launch_step(L, c->stream);
+  if (e == hipSuccess && !L.update_T)
+    e = hipMemcpyAsync(dst + al(a->fbytes), src + al(a->fbytes), a->tbytes, hipMemcpyDeviceToDevice, c->stream);
+  return e;
+}
+
 template <class S>
 static lbm_status adj_backward(lbm_adjoint* a, double dJ, double* grad_host) {
   lbm_ctx* c = a->c;
@@ -735,20 +758,16 @@ static lbm_status adj_backward(lbm_adjoint* a, double dJ, double* grad_host) {
   for (int k = a->nck - 1; k >= 0; --k) {
     const int n0 = k * a->ckpt;
     const int len = std::min(a->ckpt, a->nsteps - n0);
-    // recompute the segment's states with the fused step
-    copy_state<S>(a, a->slot_ptr(a->off_ck, k), true);
-    c->step = a->start_step + n0;
-    for (int s = 0; s < len; ++s) {
-      copy_state<S>(a, a->slot_ptr(a->off_seg, s), false);
-      if (s + 1 < len) {
-        lbm_status st = lbm_step(c, 1);
-        if (st != LBM_OK) return st;
-      }
-    }
+    // recompute the segment's states with the fused step, each straight into
+    // its slot; state 0 is the checkpoint itself
+    char* ck = a->slot_ptr(a->off_ck, k);
+    auto state_of = [&](int s) { return s == 0 ? ck : a->slot_ptr(a->off_seg, s); };
+    for (int s = 1; s < len; ++s)
+      HIP_TRY(c, step_into(a, state_of(s - 1), state_of(s), a->start_step + n0 + s - 1));
     for (int s = len - 1; s >= 0; --s) {
       const int64_t n = a->start_step + n0 + s;
       const bool th = c->p.thermal && n >= c->p.n_iso;
-      const char* state = a->slot_ptr(a->off_seg, s);
+      const char* state = state_of(s);
       HIP_TRY(c, reverse_step<S>(a, state, th));
       HIP_TRY(c, reverse_step_rest<S>(a, state, th));
     }
