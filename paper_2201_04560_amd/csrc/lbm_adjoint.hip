@@ -297,10 +297,9 @@ __global__ __launch_bounds__(kThreads) void k_ea_coef(const double* __restrict__
 }
 
 // transposed stencils: out = base1 + base2 + adjoint of phi
-__global__ __launch_bounds__(kThreads) void k_ea_gather(double* __restrict__ out, const double* __restrict__ base1,
-                                                        const double* __restrict__ base2, Geo g, Phys ph,
-                                                        Fields F) {
-  NODE_LOOP;
+__device__ __forceinline__ void ea_gather_at(double* __restrict__ out, const double* __restrict__ base1,
+                                             const double* __restrict__ base2, const Geo& g, const Phys& ph,
+                                             const Fields& F, int id, int x, int y) {
   double ph_ = F.f[F_PHILOC][id], rh = 0, uxh = 0, uyh = 0;
   for (int i = 1; i < 9; ++i) {
     // x_src = y - c_i sees this node as its neighbour i
@@ -317,11 +316,17 @@ __global__ __launch_bounds__(kThreads) void k_ea_gather(double* __restrict__ out
   F.f[F_UYE][id] += uyh;
   out[id] = (base1 ? base1[id] : 0.0) + (base2 ? base2[id] : 0.0) + ph_;
 }
+__global__ __launch_bounds__(kThreads) void k_ea_gather(double* __restrict__ out, const double* __restrict__ base1,
+                                                        const double* __restrict__ base2, Geo g, Phys ph,
+                                                        Fields F) {
+  NODE_LOOP;
+  ea_gather_at(out, base1, base2, g, ph, F, id, x, y);
+}
 
 // ----------------------------------------------------- collision adjoint
 template <class S>
-__global__ __launch_bounds__(kThreads) void k_ca(const S* __restrict__ P, Geo g, Phys ph, Fields F, int thermal) {
-  NODE_LOOP;
+__device__ __forceinline__ void ca_at(const S* __restrict__ P, const Geo& g, const Phys& ph, const Fields& F,
+                                      int thermal, int id, int x, int y) {
   double f[9], fs[9];
   for (int i = 0; i < 9; ++i) {
     f[i] = pop(P, g, i, wrapi(x - d_cx[i], g.nx), wrapi(y - d_cy[i], g.ny));
@@ -403,6 +408,22 @@ __global__ __launch_bounds__(kThreads) void k_ca(const S* __restrict__ P, Geo g,
   F.f[F_QYYH][id] = qyyh;
   F.f[F_QXYH][id] = qxyh;
   F.f[F_PSIS][id] = psih;
+}
+template <class S>
+__global__ __launch_bounds__(kThreads) void k_ca(const S* __restrict__ P, Geo g, Phys ph, Fields F, int thermal) {
+  NODE_LOOP;
+  ca_at(P, g, ph, F, thermal, id, x, y);
+}
+// the first RK stage's transposed stencils and the collision adjoint in one
+// kernel: the latter reads only its own node's outputs of the former
+template <class S>
+__global__ __launch_bounds__(kThreads) void k_ea_gather_ca(const S* __restrict__ P, double* __restrict__ out,
+                                                           const double* __restrict__ base1,
+                                                           const double* __restrict__ base2, Geo g, Phys ph,
+                                                           Fields F) {
+  NODE_LOOP;
+  ea_gather_at(out, base1, base2, g, ph, F, id, x, y);
+  ca_at(P, g, ph, F, 1, id, x, y);
 }
 
 // adjoint of F^m, Q with respect to psi (gather), then of psi(rho, T)
@@ -620,8 +641,9 @@ static hipError_t reverse_step_rest(lbm_adjoint* a, const char* state, bool ther
   const int nodes = g.nx * g.ny;
   const dim3 grid((nodes + kThreads - 1) / kThreads), blk(kThreads);
   if (thermal_on)
-    hipLaunchKernelGGL(k_ea_gather, grid, blk, 0, st, F.f[F_THAT], F.f[F_AM2], F.f[F_AM1], g, ph, F);
-  hipLaunchKernelGGL(k_ca<S>, grid, blk, 0, st, P, g, ph, F, int(thermal_on));
+    hipLaunchKernelGGL(k_ea_gather_ca<S>, grid, blk, 0, st, P, F.f[F_THAT], F.f[F_AM2], F.f[F_AM1], g, ph, F);
+  else
+    hipLaunchKernelGGL(k_ca<S>, grid, blk, 0, st, P, g, ph, F, 0);
   hipLaunchKernelGGL(k_fa, grid, blk, 0, st, g, ph, F);
   hipLaunchKernelGGL(k_sa, grid, blk, 0, st, g, F);
   return hipGetLastError();
