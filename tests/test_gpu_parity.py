@@ -391,6 +391,37 @@ def test_vaporisation512_full_size_bench_launch(precision):
         assert _rel(r, ro) < 1e-4 and _rel(T2, To) < 1e-6
 
 
+def test_fp32_vaporisation512_error_bound():
+    """The stated accuracy of the benchmark's float32 step: the 512^2
+    vaporisation workload after 2000 steps in float32 shifted storage
+    against the float64 step (itself held to the oracle above): rho within
+    1e-3, T within 1e-4 (relative to each field's max), mass within 1e-4
+    and the same liquid fraction to 1e-3 (measured: 9e-5, 8e-6, 1e-5)."""
+    print("case vaporisation512 fp32 vs fp64, 2000 steps", flush=True)
+    eos, Tsat, rv, rl = cases.coexistence()
+    Tout = 0.95 * eos.Tc
+    n = 512
+    c = dict(nx=n, ny=n, a=2.0 / 49.0, sigma=0.1, kappa=0.1, rho_l=rl, rho_v=rv, thermal=True,
+             cv=6.0, lambda_l=2 / 3, lambda_v=2 / 3, t_side_dirichlet=True, t_side_val=Tout,
+             t_bottom_kind=np.full(n, 1), t_bottom_val=np.full(n, Tout),
+             t_top_kind=np.full(n, 1), t_top_val=np.full(n, Tout), **cases.wl.DROPLET_RATES)
+    rho, T = cases.wl.droplet(n, n, 60.0, 4.6 / 5.0, rl, rv, Tsat, Tout, seed=0)
+    out = {}
+    for prec in (0, 1):
+        lat = _lat(c, precision=prec)
+        lat.init_fields(rho, None, None, T)
+        lat.step(2000)
+        r, _, _, T2 = lat.fields()
+        out[prec] = (r, T2, lat.norms()["mass"])
+        lat.close()
+    (r64, T64, m64), (r32, T32, m32) = out[0], out[1]
+    mid = 0.5 * (rl + rv)
+    errs = dict(rho=_rel(r32, r64), T=_rel(T32, T64), mass=abs(m32 / m64 - 1),
+                liquid=abs((r32 > mid).mean() - (r64 > mid).mean()))
+    print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    assert errs["rho"] < 1e-3 and errs["T"] < 1e-4 and errs["mass"] < 1e-4 and errs["liquid"] < 1e-3
+
+
 def test_huge_lattice_equals_tiled_small_one():
     """A 16384 x 16384 lattice (268 M nodes, 21 GB of float32 populations
     and temperatures, offsets far beyond 32 bits) started from a periodic
