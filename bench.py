@@ -313,12 +313,21 @@ def ladder_bench(steps0, levels=(0, 1, 2, 3), seeds=(0, 1, 2, 3), tile_cache=Non
             steps.append(L["steps"])
         return lats, steps
 
+    def make(k):
+        out = []
+        for sd in seeds:
+            L, rho, T = ladder_case(k, sd, 1, steps0)
+            lat = Lattice(L["params"])
+            lat.set_boundary(**L["boundary"])
+            lat.init_fields(rho, None, None, T)
+            out.append(lat)
+        return out
+
+    # strip height per mesh, tuned on the batched launch of that mesh's seeds
+    # (one wave per strip), which is what runs once the coarser meshes are done
+    tiles = {k: cache.tune_batch(lambda k=k: make(k), device=dev) for k in levels}
     lats32, steps = build(1)
-    tiles = {}
     for (k, sd), lat in zip(specs, lats32):
-        if k not in tiles:
-            # the batched launch runs one wave per strip: tune the height for it
-            tiles[k] = cache.tune(lat, device=dev + "/batch", waves=(1,))[0]
         lat.tile_y = tiles[k]
     log(f"bench: ladder tiles {tiles}, steps {sorted(set(steps))}")
     b = Batch(lats32)

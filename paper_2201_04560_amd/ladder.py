@@ -104,6 +104,52 @@ class TileCache:
         lattice.tile_y, lattice.strip_waves = hit
         return hit
 
+    def tune_batch(self, make_lattices, device="",
+                   candidates=(4, 6, 8, 12, 13, 16, 20, 24, 26, 32, 40, 48, 52, 64, 80, 96, 128),
+                   steps=10):
+        """Strip height for same-shaped lattices advanced together by one
+        batched launch (one wave per strip).  A batch holds n times the
+        workgroups of one lattice, so it can afford taller strips (fewer
+        recomputed halo rows) than the lattice alone.  On a miss, times the
+        batched launch for each candidate on throwaway lattices from
+        make_lattices() (initialised, same shape) and caches the fastest
+        under the lattice key + "/batch<n>".  Returns the height."""
+        lats = None
+        key = None
+        e = None
+        try:
+            lats = make_lattices()
+            n = len(lats)
+            key = self.key(lats[0].p, f"{device}/batch{n}")
+            e = self.table.get(key)
+            if e is None:
+                from .sim import Batch
+
+                best, tried = None, []
+                for ty in candidates:
+                    if ty > max(lats[0].ny, 2):
+                        continue
+                    for lat in lats:
+                        lat.tile_y = ty
+                        lat.strip_waves = 1
+                    b = Batch(lats)
+                    try:
+                        b.run([2] * n)
+                        b.run([steps] * n)
+                        ms = b.last_time()[0] / steps
+                    finally:
+                        b.close()
+                    tried.append(ty)
+                    if best is None or ms < best[1]:
+                        best = (ty, ms)
+                e = {"tile_y": best[0], "strip_waves": 1, "ms_per_step": best[1], "candidates": tried}
+                self.table[key] = e
+                self._save()
+        finally:
+            for lat in lats or []:
+                lat.close()
+        return int(e["tile_y"])
+
     def _save(self):
         d = os.path.dirname(self.path)
         os.makedirs(d, exist_ok=True)

@@ -163,6 +163,30 @@ def test_tile_candidates_fill_whole_rounds():
         assert 22 * (-(-1000 // ty)) <= per_simd * slots < 22 * (-(-1000 // (ty - 1)))
 
 
+def test_tune_batch_caches_a_candidate(tmp_path):
+    """The batched-launch tuner picks one of its candidates for the group,
+    stores it under the lattice key + /batch<n>, and leaves the lattices it
+    timed closed."""
+    print("case tune batch", flush=True)
+    from paper_2201_04560_amd.ladder import TileCache
+
+    made = []
+
+    def make():
+        lats = [_make(_pool_case(96, 64, s, gy=0.0), precision=1) for s in (1, 2)]
+        made.extend(lats)
+        return lats
+
+    cache = TileCache(str(tmp_path / "tiles.json"))
+    ty = cache.tune_batch(make, device="test", candidates=(4, 8, 16), steps=3)
+    assert ty in (4, 8, 16)
+    key = [k for k in cache.table if k.endswith("test/batch2")]
+    assert len(key) == 1 and cache.table[key[0]]["tile_y"] == ty
+    assert all(not lat._ctx.value for lat in made)
+    again = TileCache(str(tmp_path / "tiles.json"))
+    assert again.tune_batch(make, device="test", candidates=(4, 8, 16), steps=3) == ty
+
+
 def test_two_waves_only_below_4gib_of_planes():
     """The two-wave march addresses the 9 population planes with 32-bit
     offsets and wraps rows with one correction: a lattice whose planes span
