@@ -548,8 +548,17 @@ struct lbm_adjoint {
   Fields F{};
   Geo g{};
   BC bc{};
+  // the backward replays segment k - 1 on a stream of its own while segment
+  // k is reversed; segment k's states use slot set k & 1
+  hipStream_t replay = nullptr;
+  hipEvent_t ev_start = nullptr, ev_replayed[2] = {nullptr, nullptr}, ev_reversed[2] = {nullptr, nullptr};
 
   char* slot_ptr(size_t off, int k) const { return buf + off + size_t(k) * slot; }
+  ~lbm_adjoint() {
+    for (hipEvent_t e : {ev_start, ev_replayed[0], ev_replayed[1], ev_reversed[0], ev_reversed[1]})
+      if (e) (void)hipEventDestroy(e);
+    if (replay) (void)hipStreamDestroy(replay);
+  }
 };
 
 static void adj_sizes(const lbm_params& p, int nsteps, int ckpt, size_t& fbytes, size_t& tbytes, size_t& slot,
@@ -564,7 +573,7 @@ static void adj_sizes(const lbm_params& p, int nsteps, int ckpt, size_t& fbytes,
   const int nblk = int((nodes + kThreads - 1) / kThreads);
   size_t o = 0;
   offs[0] = o; o += size_t(nck) * slot;                      // checkpoints
-  offs[1] = o; o += size_t(ckpt) * slot;                     // segment states
+  offs[1] = o; o += 2 * size_t(ckpt) * slot;                 // segment states, two sets
   offs[2] = o; o += slot;                                    // final state
   offs[3] = o; o += size_t(kNumFields) * al(nodes * 8);      // float64 fields
   offs[4] = o; o += al(size_t(p.nx) * 8);                    // gradient
@@ -701,6 +710,15 @@ lbm_status lbm_adjoint_create(lbm_ctx* c, int32_t nsteps, int32_t ckpt_every, do
   a->g = Geo{c->p.nx, c->p.ny, c->L.pitch, c->L.plane, c->p.precision == LBM_FP32_SHIFTED, c->ph.rho_ref};
   const Tables t = c->tables();
   a->bc = BC{t.tk_b, t.tk_t, t.tv_b, t.tv_t, c->p.t_side_dirichlet, c->p.t_side_val};
+  // default priority, like every stream of the library
+  hipError_t e = hipStreamCreateWithFlags(&a->replay, hipStreamNonBlocking);
+  for (hipEvent_t* ev : {&a->ev_start, &a->ev_replayed[0], &a->ev_replayed[1], &a->ev_reversed[0],
+                         &a->ev_reversed[1]})
+    if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    delete a;
+    return fail(c, LBM_E_HIP, "adjoint: stream or event creation failed");
+  }
   *out = a;
   return LBM_OK;
 }
@@ -748,7 +766,7 @@ static lbm_status adj_forward(lbm_adjoint* a, double* J) {
 // slot `dst` (same layout as the context's buffers, same launch as lbm_step
 // at step index n, so the states are bit-identical to the forward run's);
 // without the energy update T is carried over
-static hipError_t step_into(lbm_adjoint* a, const char* src, char* dst, int64_t n) {
+static hipError_t step_into(lbm_adjoint* a, const char* src, char* dst, int64_t n, hipStream_t st) {
   lbm_ctx* c = a->c;
   LaunchStep L = step_args(c);
   L.fin = src;
@@ -757,9 +775,9 @@ static hipError_t step_into(lbm_adjoint* a, const char* src, char* dst, int64_t 
   L.Tout = dst + al(a->fbytes);
   L.update_T = c->p.thermal && n >= c->p.n_iso;
   L.want_mass = 0;
-  hipError_t e = launch_step(L, c->stream);
+  hipError_t e = launch_step(L, st);
   if (e == hipSuccess && !L.update_T)
-    e = hipMemcpyAsync(dst + al(a->fbytes), src + al(a->fbytes), a->tbytes, hipMemcpyDeviceToDevice, c->stream);
+    e = hipMemcpyAsync(dst + al(a->fbytes), src + al(a->fbytes), a->tbytes, hipMemcpyDeviceToDevice, st);
   return e;
 }
 
@@ -777,22 +795,40 @@ static lbm_status adj_backward(lbm_adjoint* a, double dJ, double* grad_host) {
   hipLaunchKernelGGL(k_seed<S>, grid, blk, 0, c->stream, reinterpret_cast<const S*>(fin), g, a->rm, a->wd, dJ,
                      a->F);
   HIP_TRY(c, hipGetLastError());
-  for (int k = a->nck - 1; k >= 0; --k) {
+  // state s of segment k: the checkpoint for s = 0, else slot s of set k & 1
+  auto state_of = [&](int k, int s) {
+    return s == 0 ? a->slot_ptr(a->off_ck, k) : a->slot_ptr(a->off_seg, (k & 1) * a->ckpt + s);
+  };
+  auto seg_len = [&](int k) { return std::min(a->ckpt, a->nsteps - k * a->ckpt); };
+  // replay segment k with the fused step on the replay stream, each state
+  // written straight into its slot
+  auto replay = [&](int k) -> hipError_t {
     const int n0 = k * a->ckpt;
-    const int len = std::min(a->ckpt, a->nsteps - n0);
-    // recompute the segment's states with the fused step, each straight into
-    // its slot; state 0 is the checkpoint itself
-    char* ck = a->slot_ptr(a->off_ck, k);
-    auto state_of = [&](int s) { return s == 0 ? ck : a->slot_ptr(a->off_seg, s); };
-    for (int s = 1; s < len; ++s)
-      HIP_TRY(c, step_into(a, state_of(s - 1), state_of(s), a->start_step + n0 + s - 1));
-    for (int s = len - 1; s >= 0; --s) {
+    for (int s = 1; s < seg_len(k); ++s) {
+      const hipError_t e = step_into(a, state_of(k, s - 1), state_of(k, s), a->start_step + n0 + s - 1, a->replay);
+      if (e != hipSuccess) return e;
+    }
+    return hipEventRecord(a->ev_replayed[k & 1], a->replay);
+  };
+  HIP_TRY(c, hipEventRecord(a->ev_start, c->stream));
+  HIP_TRY(c, hipStreamWaitEvent(a->replay, a->ev_start, 0));
+  HIP_TRY(c, replay(a->nck - 1));
+  for (int k = a->nck - 1; k >= 0; --k) {
+    HIP_TRY(c, hipStreamWaitEvent(c->stream, a->ev_replayed[k & 1], 0));
+    if (k > 0) {
+      // set (k - 1) & 1 was last read by the reversal of segment k + 1
+      if (k + 1 < a->nck) HIP_TRY(c, hipStreamWaitEvent(a->replay, a->ev_reversed[(k + 1) & 1], 0));
+      HIP_TRY(c, replay(k - 1));
+    }
+    const int n0 = k * a->ckpt;
+    for (int s = seg_len(k) - 1; s >= 0; --s) {
       const int64_t n = a->start_step + n0 + s;
       const bool th = c->p.thermal && n >= c->p.n_iso;
-      const char* state = state_of(s);
+      const char* state = state_of(k, s);
       HIP_TRY(c, reverse_step<S>(a, state, th));
       HIP_TRY(c, reverse_step_rest<S>(a, state, th));
     }
+    HIP_TRY(c, hipEventRecord(a->ev_reversed[k & 1], c->stream));
   }
   hipLaunchKernelGGL(k_grad_init, dim3((g.nx + kThreads - 1) / kThreads), blk, 0, c->stream, a->F.f[F_THAT], grad,
                      g, a->bc);
