@@ -432,7 +432,7 @@ def adjoint_bench(nsteps=500, ckpt=50, n=256, fd_entries=8, h=1e-4):
                      "backward_over_forward": round(b_ms / (t_plain * 1e3), 2),
                      "gradient_over_forward": round((f_ms + b_ms) / (t_plain * 1e3), 2),
                      "speedup_vs_central_fd": round(2 * n * t_plain * 1e3 / (f_ms + b_ms), 1)}
-        if name == "fp64":
+        if name == "fp64" and fd_entries > 0:
             ent = np.linspace(16, n - 17, fd_entries).astype(int)
             errs = []
             for x in ent:
@@ -559,9 +559,10 @@ def main():
     ap.add_argument("--no-sizing", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fp32", "fp64", "both"], default="both")
-    ap.add_argument("--profile-case", choices=["vaporisation512", "pool4096"], default=None,
+    ap.add_argument("--profile-case", choices=["vaporisation512", "pool4096", "adjoint256"], default=None,
                     help="profiling run: only this case (precision from --only), --steps steps, "
-                         "plus a device copy of --copy-mib MiB (counter calibration); no JSON")
+                         "plus a device copy of --copy-mib MiB (counter calibration); no JSON. "
+                         "adjoint256: the 256^2 x 500-step heater gradient in both precisions")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--tile-y", type=int, default=0)
     ap.add_argument("--strip-waves", type=int, default=0,
@@ -615,6 +616,12 @@ def main():
 
     tune = None if (args.tile_y or args.no_autotune) else TileCache(args.tile_cache)
 
+    if args.profile_case == "adjoint256":
+        r = adjoint_bench(fd_entries=0)
+        for name in ("fp32", "fp64"):
+            log(f"profile: adjoint256 {name} backward {r[name]['backward_ms']} ms, checkpointed forward "
+                f"{r[name]['checkpointed_forward_ms']} ms, plain forward {r[name]['plain_forward_ms']} ms")
+        return
     if args.profile_case:
         pcase = vaporisation_case() if args.profile_case == "vaporisation512" else pool_case()
         for name, prec in (("fp32", LBM_FP32_SHIFTED), ("fp64", LBM_FP64)):

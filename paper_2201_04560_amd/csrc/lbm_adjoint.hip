@@ -68,8 +68,11 @@ enum Field {
   F_THAT, F_AM2, F_AM1, F_TSH, F_PHILOC,
   F_CUX, F_CUY, F_C1, F_C2X, F_C2Y, F_C3, F_DX, F_DY,
   F_RHOE, F_UXE, F_UYE,
-  F_FXH, F_FYH, F_QXXH, F_QYYH, F_QXYH, F_PSIS, F_RHOPSI,
-  F_FH0, F_PH0 = F_FH0 + 9, kNumFields = F_PH0 + 9
+  F_FXH, F_FYH, F_QXXH, F_QYYH, F_QXYH, F_PSIS,
+  // two sets (reversed steps alternate): adjoints of rho through psi and of
+  // the streamed populations, written by one reversed step, gathered by the next
+  F_RHOPSI, F_RHOPSI1, F_FH0, F_FH1 = F_FH0 + 9,
+  F_PH0 = F_FH1 + 9, kNumFields = F_PH0 + 9
 };
 
 struct Fields {
@@ -102,7 +105,8 @@ __device__ __forceinline__ double dir_val(const BC& bc, int x, int y, int nx) {
 template <class S>
 __device__ __forceinline__ double pop(const S* P, const Geo& g, int i, int x, int y) {
   const double v = double(P[i * g.plane + (long long)y * g.pitch + x]);
-  return g.fp32 ? v + d_we[i] * g.rho_ref : v;
+  if constexpr (sizeof(S) == 4) return v + d_we[i] * g.rho_ref;
+  else return v;
 }
 
 // T (dp/dT)_rho and its partial derivatives (Eq. peng-robinson)
@@ -138,6 +142,7 @@ __global__ __launch_bounds__(kThreads) void k_fm1(const S* __restrict__ P, const
                                                   Phys ph, Fields F) {
   NODE_LOOP;
   double r = 0, jx = 0, jy = 0;
+  #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const double fi = pop(P, g, i, wrapi(x - d_cx[i], g.nx), wrapi(y - d_cy[i], g.ny));
     r += fi;
@@ -157,6 +162,7 @@ __global__ __launch_bounds__(kThreads) void k_fm2(Geo g, Phys ph, Fields F) {
   const double* psi = F.f[F_PSI];
   const double p0 = psi[id];
   double sx = 0, sy = 0, qxx = 0, qyy = 0, qxy = 0;
+  #pragma unroll
   for (int i = 1; i < 9; ++i) {
     const double pn = NB(psi, i);
     sx += d_wi[i] * pn * d_cx[i];
@@ -188,6 +194,7 @@ __device__ double energy_K(PhiF phi, const Fields& F, const Geo& g, const Phys& 
   const int id = y * g.nx + x;
   const double p0 = phi(x, y);
   double gx = 0, gy = 0, lap = 0, grx = 0, gry = 0, du = 0;
+  #pragma unroll
   for (int i = 1; i < 9; ++i) {
     const int xn = wrapi(x + d_cx[i], g.nx), yn = wrapi(y + d_cy[i], g.ny);
     const int n = yn * g.nx + xn;
@@ -255,6 +262,7 @@ __global__ __launch_bounds__(kThreads) void k_ea_coef(const double* __restrict__
   const double w = wfac * ea_mask(gin, am, grad, g, bc, id, x, y);
   const double p0 = phi_arr[id];
   double gx = 0, gy = 0, lap = 0, grx = 0, gry = 0, du = 0;
+  #pragma unroll
   for (int i = 1; i < 9; ++i) {
     const int n = wrapi(y + d_cy[i], g.ny) * g.nx + wrapi(x + d_cx[i], g.nx);
     const double pn = phi_arr[n];
@@ -301,6 +309,7 @@ __device__ __forceinline__ void ea_gather_at(double* __restrict__ out, const dou
                                              const double* __restrict__ base2, const Geo& g, const Phys& ph,
                                              const Fields& F, int id, int x, int y) {
   double ph_ = F.f[F_PHILOC][id], rh = 0, uxh = 0, uyh = 0;
+  #pragma unroll
   for (int i = 1; i < 9; ++i) {
     // x_src = y - c_i sees this node as its neighbour i
     const int n = wrapi(y - d_cy[i], g.ny) * g.nx + wrapi(x - d_cx[i], g.nx);
@@ -324,13 +333,25 @@ __global__ __launch_bounds__(kThreads) void k_ea_gather(double* __restrict__ out
 }
 
 // ----------------------------------------------------- collision adjoint
+// The adjoint of the pull-stream f_i(x) = P_i(x - c_i) is gathered here: the
+// adjoint of the collided population i at x is that of the streamed one at
+// x + c_i plus that of rho there through psi, both written by the previous
+// reversed step into the other set.  The first reversed step reads the seed
+// (F_PH0) instead.  This step writes its own outputs into set `set`.
 template <class S>
 __device__ __forceinline__ void ca_at(const S* __restrict__ P, const Geo& g, const Phys& ph, const Fields& F,
-                                      int thermal, int id, int x, int y) {
+                                      int thermal, int set, bool seeded, int id, int x, int y) {
   double f[9], fs[9];
+  const double* rpsi = F.f[F_RHOPSI + (set ^ 1)];
+  #pragma unroll
   for (int i = 0; i < 9; ++i) {
     f[i] = pop(P, g, i, wrapi(x - d_cx[i], g.nx), wrapi(y - d_cy[i], g.ny));
-    fs[i] = F.f[F_PH0 + i][id];
+    if (seeded) {
+      fs[i] = F.f[F_PH0 + i][id];
+    } else {
+      const int n = wrapi(y + d_cy[i], g.ny) * g.nx + wrapi(x + d_cx[i], g.nx);
+      fs[i] = F.f[F_FH0 + 9 * (set ^ 1) + i][n] + rpsi[n];
+    }
   }
   const double r = F.f[F_RHO][id], ux = F.f[F_UX][id], uy = F.f[F_UY][id];
   const double fx = F.f[F_FX][id], fy = F.f[F_FY][id], psi = F.f[F_PSI][id];
@@ -339,8 +360,10 @@ __device__ __forceinline__ void ca_at(const S* __restrict__ P, const Geo& g, con
   const double snu = 1.0 / (3.0 * eta + 0.5);
   const double dsnu = -3.0 * (ph.eta_l - ph.eta_v) * ph.inv_drho * snu * snu;
   double m[9], ms[9];
+  #pragma unroll
   for (int k = 0; k < 9; ++k) {
     double s = 0, t = 0;
+    #pragma unroll
     for (int i = 0; i < 9; ++i) {
       s += d_M[k][i] * f[i];
       t += d_M[k][i] * fs[i];
@@ -356,6 +379,7 @@ __device__ __forceinline__ void ca_at(const S* __restrict__ P, const Geo& g, con
   const double lam[9] = {1.0, ph.s_e, ph.s_z, ph.s_j, ph.s_q, ph.s_j, ph.s_q, snu, snu};
   // direct path m -> m*: (1 - Lambda); rho row: s_rho cancels (m_0 = meq_0)
   double mh[9];
+  #pragma unroll
   for (int k = 0; k < 9; ++k) mh[k] = (1.0 - lam[k]) * ms[k];
   double rh = ms[0] * 1.0;  // meq_0 = rho with rate lam[0] = 1 (same total as any s_rho)
   double uxh = 0, uyh = 0;
@@ -397,10 +421,12 @@ __device__ __forceinline__ void ca_at(const S* __restrict__ P, const Geo& g, con
   fyh += 0.5 * uyh / r;
   rh -= (uxh * ux + uyh * uy) / r;
   // f* = M^-1 m*, m = M f, rho = sum f, j = sum f c
+  #pragma unroll
   for (int i = 0; i < 9; ++i) {
     double s = 0;
+    #pragma unroll
     for (int k = 0; k < 9; ++k) s += d_M[k][i] * mh[k];
-    F.f[F_FH0 + i][id] = s + rh + d_cx[i] * jxh + d_cy[i] * jyh;
+    F.f[F_FH0 + 9 * set + i][id] = s + rh + d_cx[i] * jxh + d_cy[i] * jyh;
   }
   F.f[F_FXH][id] = fxh;
   F.f[F_FYH][id] = fyh;
@@ -410,9 +436,10 @@ __device__ __forceinline__ void ca_at(const S* __restrict__ P, const Geo& g, con
   F.f[F_PSIS][id] = psih;
 }
 template <class S>
-__global__ __launch_bounds__(kThreads) void k_ca(const S* __restrict__ P, Geo g, Phys ph, Fields F, int thermal) {
+__global__ __launch_bounds__(kThreads) void k_ca(const S* __restrict__ P, Geo g, Phys ph, Fields F, int thermal,
+                                                 int set, int seeded) {
   NODE_LOOP;
-  ca_at(P, g, ph, F, thermal, id, x, y);
+  ca_at(P, g, ph, F, thermal, set, seeded != 0, id, x, y);
 }
 // the first RK stage's transposed stencils and the collision adjoint in one
 // kernel: the latter reads only its own node's outputs of the former
@@ -420,14 +447,15 @@ template <class S>
 __global__ __launch_bounds__(kThreads) void k_ea_gather_ca(const S* __restrict__ P, double* __restrict__ out,
                                                            const double* __restrict__ base1,
                                                            const double* __restrict__ base2, Geo g, Phys ph,
-                                                           Fields F) {
+                                                           Fields F, int set, int seeded) {
   NODE_LOOP;
   ea_gather_at(out, base1, base2, g, ph, F, id, x, y);
-  ca_at(P, g, ph, F, 1, id, x, y);
+  ca_at(P, g, ph, F, 1, set, seeded != 0, id, x, y);
 }
 
-// adjoint of F^m, Q with respect to psi (gather), then of psi(rho, T)
-__global__ __launch_bounds__(kThreads) void k_fa(Geo g, Phys ph, Fields F) {
+// adjoint of F^m, Q with respect to psi (gather), then of psi(rho, T); the
+// part that reaches rho goes to set `set`
+__global__ __launch_bounds__(kThreads) void k_fa(Geo g, Phys ph, Fields F, int set) {
   NODE_LOOP;
   const double* psi = F.f[F_PSI];
   const double p0 = psi[id];
@@ -437,6 +465,7 @@ __global__ __launch_bounds__(kThreads) void k_fa(Geo g, Phys ph, Fields F) {
               F.f[F_QYYH][id] * F.f[F_QYY][id] + F.f[F_QXYH][id] * F.f[F_QXY][id]) /
                  p0 -
              kG2 * p0 * (F.f[F_QXXH][id] + F.f[F_QYYH][id]);
+  #pragma unroll
   for (int i = 1; i < 9; ++i) {
     const int n = wrapi(y - d_cy[i], g.ny) * g.nx + wrapi(x - d_cx[i], g.nx);
     const double cx = d_cx[i], cy = d_cy[i];
@@ -447,23 +476,15 @@ __global__ __launch_bounds__(kThreads) void k_fa(Geo g, Phys ph, Fields F) {
   const double r = F.f[F_RHO][id];
   const double t = F.f[F_T][id];
   const double inv = 1.0 / (ph.G * p0);
-  F.f[F_RHOPSI][id] = h * (dp_drho(r, t, ph) - 1.0 / 3.0) * inv;
+  F.f[F_RHOPSI + set][id] = h * (dp_drho(r, t, ph) - 1.0 / 3.0) * inv;
   F.f[F_THAT][id] += h * dp_dT(r, t, ph) * inv;
-}
-
-// adjoint of the pull-stream f_i(x) = P_i(x - c_i)
-__global__ __launch_bounds__(kThreads) void k_sa(Geo g, Fields F) {
-  NODE_LOOP;
-  for (int i = 0; i < 9; ++i) {
-    const int n = wrapi(y + d_cy[i], g.ny) * g.nx + wrapi(x + d_cx[i], g.nx);
-    F.f[F_PH0 + i][id] = F.f[F_FH0 + i][n] + F.f[F_RHOPSI][n];
-  }
 }
 
 // ------------------------------------------------ objective and its seed
 template <class S>
 __device__ __forceinline__ double rho_read(const S* P, const Geo& g, int x, int y) {
   double r = 0;
+  #pragma unroll
   for (int i = 0; i < 9; ++i) r += pop(P, g, i, wrapi(x - d_cx[i], g.nx), wrapi(y - d_cy[i], g.ny));
   return r;
 }
@@ -641,7 +662,7 @@ static hipError_t reverse_step(lbm_adjoint* a, const char* state, bool thermal_o
 }
 
 template <class S>
-static hipError_t reverse_step_rest(lbm_adjoint* a, const char* state, bool thermal_on) {
+static hipError_t reverse_step_rest(lbm_adjoint* a, const char* state, bool thermal_on, int64_t j) {
   const S* P = reinterpret_cast<const S*>(state);
   const Geo& g = a->g;
   const Phys& ph = a->c->ph;
@@ -649,12 +670,15 @@ static hipError_t reverse_step_rest(lbm_adjoint* a, const char* state, bool ther
   hipStream_t st = a->c->stream;
   const int nodes = g.nx * g.ny;
   const dim3 grid((nodes + kThreads - 1) / kThreads), blk(kThreads);
+  // j counts the reversed steps from 0: the first reads the seed, each later
+  // one gathers what the previous one wrote into the other set
+  const int set = int(j & 1), seeded = j == 0;
   if (thermal_on)
-    hipLaunchKernelGGL(k_ea_gather_ca<S>, grid, blk, 0, st, P, F.f[F_THAT], F.f[F_AM2], F.f[F_AM1], g, ph, F);
+    hipLaunchKernelGGL(k_ea_gather_ca<S>, grid, blk, 0, st, P, F.f[F_THAT], F.f[F_AM2], F.f[F_AM1], g, ph, F, set,
+                       seeded);
   else
-    hipLaunchKernelGGL(k_ca<S>, grid, blk, 0, st, P, g, ph, F, 0);
-  hipLaunchKernelGGL(k_fa, grid, blk, 0, st, g, ph, F);
-  hipLaunchKernelGGL(k_sa, grid, blk, 0, st, g, F);
+    hipLaunchKernelGGL(k_ca<S>, grid, blk, 0, st, P, g, ph, F, 0, set, seeded);
+  hipLaunchKernelGGL(k_fa, grid, blk, 0, st, g, ph, F, set);
   return hipGetLastError();
 }
 
@@ -826,7 +850,7 @@ static lbm_status adj_backward(lbm_adjoint* a, double dJ, double* grad_host) {
       const bool th = c->p.thermal && n >= c->p.n_iso;
       const char* state = state_of(k, s);
       HIP_TRY(c, reverse_step<S>(a, state, th));
-      HIP_TRY(c, reverse_step_rest<S>(a, state, th));
+      HIP_TRY(c, reverse_step_rest<S>(a, state, th, a->start_step + a->nsteps - 1 - n));
     }
     HIP_TRY(c, hipEventRecord(a->ev_reversed[k & 1], c->stream));
   }
