@@ -273,11 +273,12 @@ lbm_status lbm_planar_gamma(double a, double b, double R, double omega, double G
  * The forward pass runs the fused step on the context and stores a
  * checkpoint every ckpt_every steps in dev_buf (caller-owned, 256-byte
  * aligned, >= lbm_adjoint_bytes; it also holds two sets of ckpt_every
- * recomputed states and the float64 adjoint fields).  The backward pass
- * recomputes each segment with the same kernel (identical trajectory), the
- * next one on a stream of the adjoint's own while the current one is
- * reversed step by step on the context stream; it leaves the context at the
- * end state of the forward pass. */
+ * recomputed states with 13 float64 forward fields per node and step, and
+ * the float64 adjoint fields).  The backward pass recomputes each segment with
+ * the same kernel (identical trajectory) and each step's forward quantities
+ * from its state, the next segment on a stream of the adjoint's own while the
+ * current one is reversed step by step on the context stream; it leaves the
+ * context at the end state of the forward pass. */
 typedef struct lbm_adjoint lbm_adjoint;
 lbm_status lbm_adjoint_bytes(const lbm_params* p, int32_t nsteps, int32_t ckpt_every, size_t* bytes);
 lbm_status lbm_adjoint_create(lbm_ctx* ctx, int32_t nsteps, int32_t ckpt_every, double rho_mid, double width,

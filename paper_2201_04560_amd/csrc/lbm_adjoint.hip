@@ -79,6 +79,12 @@ struct Fields {
   double* f[kNumFields];
 };
 
+// the forward quantities each reversed step recomputes from its stored state
+// (written by k_fm1, k_fm2, k_fm3, read by the adjoint kernels); they are kept
+// per step of a segment, so that the recompute runs beside the reversal
+constexpr int kFwd[] = {F_RHO, F_JX, F_JY, F_PSI, F_T, F_FX, F_FY, F_QXX, F_QYY, F_QXY, F_UX, F_UY, F_TS};
+constexpr int kNumFwd = sizeof(kFwd) / sizeof(kFwd[0]);
+
 struct BC {
   const int32_t* tk_b;
   const int32_t* tk_t;
@@ -561,7 +567,7 @@ struct lbm_adjoint {
   char* buf = nullptr;
   size_t bytes = 0;
   size_t fbytes = 0, tbytes = 0, slot = 0;
-  size_t off_ck = 0, off_seg = 0, off_fin = 0, off_fields = 0, off_grad = 0, off_part = 0, off_out = 0;
+  size_t off_ck = 0, off_seg = 0, off_fin = 0, off_fields = 0, off_grad = 0, off_part = 0, off_out = 0, off_fwd = 0;
   int64_t start_step = 0;
   double m0 = 0;
   bool forward_done = false;
@@ -575,6 +581,14 @@ struct lbm_adjoint {
   hipEvent_t ev_start = nullptr, ev_replayed[2] = {nullptr, nullptr}, ev_reversed[2] = {nullptr, nullptr};
 
   char* slot_ptr(size_t off, int k) const { return buf + off + size_t(k) * slot; }
+  // the fields with the forward quantities of step s of segment k in place
+  Fields fields_at(int k, int s) const {
+    Fields r = F;
+    const size_t fb = al(size_t(g.nx) * g.ny * 8);
+    char* base = buf + off_fwd + (size_t((k & 1) * ckpt + s) * kNumFwd) * fb;
+    for (int j = 0; j < kNumFwd; ++j) r.f[kFwd[j]] = reinterpret_cast<double*>(base + size_t(j) * fb);
+    return r;
+  }
   ~lbm_adjoint() {
     for (hipEvent_t e : {ev_start, ev_replayed[0], ev_replayed[1], ev_reversed[0], ev_reversed[1]})
       if (e) (void)hipEventDestroy(e);
@@ -583,7 +597,7 @@ struct lbm_adjoint {
 };
 
 static void adj_sizes(const lbm_params& p, int nsteps, int ckpt, size_t& fbytes, size_t& tbytes, size_t& slot,
-                      size_t& total, size_t offs[7]) {
+                      size_t& total, size_t offs[8]) {
   Layout L;
   make_layout(p, L);
   fbytes = size_t(9 * L.plane) * L.elem;
@@ -600,6 +614,7 @@ static void adj_sizes(const lbm_params& p, int nsteps, int ckpt, size_t& fbytes,
   offs[4] = o; o += al(size_t(p.nx) * 8);                    // gradient
   offs[5] = o; o += al(size_t(nblk) * 8);                    // partial sums
   offs[6] = o; o += 256;                                     // scalar out
+  offs[7] = o; o += 2 * size_t(ckpt) * kNumFwd * al(nodes * 8);  // recomputed forward fields, two sets
   total = o;
 }
 
@@ -634,22 +649,33 @@ static hipError_t liquid_mass(lbm_adjoint* a, const char* state, double* out_dev
   return hipGetLastError();
 }
 
-// one reversed step at the state stored in `state` (step index n)
+// the forward quantities of the step at the state stored in `state`, into
+// the per-step fields F (on the replay stream, after the state's replay)
 template <class S>
-static hipError_t reverse_step(lbm_adjoint* a, const char* state, bool thermal_on) {
+static hipError_t recompute_step(const lbm_adjoint* a, const char* state, bool thermal_on, const Fields& F,
+                                 hipStream_t st) {
   const S* P = reinterpret_cast<const S*>(state);
   const S* T = reinterpret_cast<const S*>(state + al(a->fbytes));
   const Geo& g = a->g;
   const Phys& ph = a->c->ph;
-  Fields& F = a->F;
-  double* grad = reinterpret_cast<double*>(a->buf + a->off_grad);
-  hipStream_t st = a->c->stream;
   const int nodes = g.nx * g.ny;
   const dim3 grid((nodes + kThreads - 1) / kThreads), blk(kThreads);
   hipLaunchKernelGGL(k_fm1<S>, grid, blk, 0, st, P, T, g, ph, F);
   hipLaunchKernelGGL(k_fm2, grid, blk, 0, st, g, ph, F);
+  if (thermal_on) hipLaunchKernelGGL(k_fm3, grid, blk, 0, st, g, ph, a->bc, F);
+  return hipGetLastError();
+}
+
+// the reversed energy update of one step, F holding the step's forward
+// quantities
+static hipError_t reverse_energy(lbm_adjoint* a, bool thermal_on, const Fields& F) {
+  const Geo& g = a->g;
+  const Phys& ph = a->c->ph;
+  double* grad = reinterpret_cast<double*>(a->buf + a->off_grad);
+  hipStream_t st = a->c->stream;
+  const int nodes = g.nx * g.ny;
+  const dim3 grid((nodes + kThreads - 1) / kThreads), blk(kThreads);
   if (thermal_on) {
-    hipLaunchKernelGGL(k_fm3, grid, blk, 0, st, g, ph, a->bc, F);
     // stage 2: T' = BC(T + K(T*))
     hipLaunchKernelGGL(k_ea_coef<true>, grid, blk, 0, st, F.f[F_THAT], F.f[F_AM2], grad, a->bc, F.f[F_TS], 1.0, g,
                        ph, F);
@@ -662,11 +688,11 @@ static hipError_t reverse_step(lbm_adjoint* a, const char* state, bool thermal_o
 }
 
 template <class S>
-static hipError_t reverse_step_rest(lbm_adjoint* a, const char* state, bool thermal_on, int64_t j) {
+static hipError_t reverse_step_rest(lbm_adjoint* a, const char* state, bool thermal_on, int64_t j,
+                                    const Fields& F) {
   const S* P = reinterpret_cast<const S*>(state);
   const Geo& g = a->g;
   const Phys& ph = a->c->ph;
-  Fields& F = a->F;
   hipStream_t st = a->c->stream;
   const int nodes = g.nx * g.ny;
   const dim3 grid((nodes + kThreads - 1) / kThreads), blk(kThreads);
@@ -688,7 +714,7 @@ lbm_status lbm_adjoint_bytes(const lbm_params* p, int32_t nsteps, int32_t ckpt_e
   if (!bytes) return LBM_E_INVAL;
   lbm_status s = adj_check_params(p, nsteps, ckpt_every);
   if (s != LBM_OK) return s;
-  size_t fb, tb, sl, tot, offs[7];
+  size_t fb, tb, sl, tot, offs[8];
   adj_sizes(*p, nsteps, ckpt_every, fb, tb, sl, tot, offs);
   *bytes = tot;
   return LBM_OK;
@@ -705,7 +731,7 @@ lbm_status lbm_adjoint_create(lbm_ctx* c, int32_t nsteps, int32_t ckpt_every, do
   if (!(width > 0)) return fail(c, LBM_E_INVAL, "width must be > 0");
   if (!dev_buf || reinterpret_cast<uintptr_t>(dev_buf) % 256)
     return fail(c, LBM_E_INVAL, "adjoint buffer must be non-null and 256-byte aligned");
-  size_t offs[7], tot;
+  size_t offs[8], tot;
   lbm_adjoint* a = new (std::nothrow) lbm_adjoint();
   if (!a) return LBM_E_NOMEM;
   adj_sizes(c->p, nsteps, ckpt_every, a->fbytes, a->tbytes, a->slot, tot, offs);
@@ -728,6 +754,7 @@ lbm_status lbm_adjoint_create(lbm_ctx* c, int32_t nsteps, int32_t ckpt_every, do
   a->off_grad = offs[4];
   a->off_part = offs[5];
   a->off_out = offs[6];
+  a->off_fwd = offs[7];
   const size_t nodes = size_t(c->p.nx) * c->p.ny;
   for (int k = 0; k < kNumFields; ++k)
     a->F.f[k] = reinterpret_cast<double*>(a->buf + a->off_fields + size_t(k) * al(nodes * 8));
@@ -825,11 +852,18 @@ static lbm_status adj_backward(lbm_adjoint* a, double dJ, double* grad_host) {
   };
   auto seg_len = [&](int k) { return std::min(a->ckpt, a->nsteps - k * a->ckpt); };
   // replay segment k with the fused step on the replay stream, each state
-  // written straight into its slot
+  // written straight into its slot, then recompute each step's forward
+  // quantities from its state
   auto replay = [&](int k) -> hipError_t {
     const int n0 = k * a->ckpt;
     for (int s = 1; s < seg_len(k); ++s) {
       const hipError_t e = step_into(a, state_of(k, s - 1), state_of(k, s), a->start_step + n0 + s - 1, a->replay);
+      if (e != hipSuccess) return e;
+    }
+    for (int s = 0; s < seg_len(k); ++s) {
+      const int64_t n = a->start_step + n0 + s;
+      const hipError_t e = recompute_step<S>(a, state_of(k, s), c->p.thermal && n >= c->p.n_iso,
+                                             a->fields_at(k, s), a->replay);
       if (e != hipSuccess) return e;
     }
     return hipEventRecord(a->ev_replayed[k & 1], a->replay);
@@ -849,8 +883,9 @@ static lbm_status adj_backward(lbm_adjoint* a, double dJ, double* grad_host) {
       const int64_t n = a->start_step + n0 + s;
       const bool th = c->p.thermal && n >= c->p.n_iso;
       const char* state = state_of(k, s);
-      HIP_TRY(c, reverse_step<S>(a, state, th));
-      HIP_TRY(c, reverse_step_rest<S>(a, state, th, a->start_step + a->nsteps - 1 - n));
+      const Fields F = a->fields_at(k, s);
+      HIP_TRY(c, reverse_energy(a, th, F));
+      HIP_TRY(c, reverse_step_rest<S>(a, state, th, a->start_step + a->nsteps - 1 - n, F));
     }
     HIP_TRY(c, hipEventRecord(a->ev_reversed[k & 1], c->stream));
   }
