@@ -44,6 +44,28 @@ def test_adjoint_fp64_matches_oracle_gradient(nsteps, ckpt):
     assert g[0] == 0.0 and g[-1] == 0.0
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_adjoint_with_isothermal_start(precision):
+    """16 x 14, energy equation off for the first 5 of 12 steps (segments of
+    5, 5, 2): the reversed steps before n_iso have no energy adjoint and their
+    recompute no first RK stage.  Float64 storage against the oracle's
+    complex-step gradient; float32 shifted storage against that too: its
+    states are rounded to 2^-24 relative each step, 4.4e-7 measured over
+    these 12 steps, bound 1e-5."""
+    print(f"case adjoint n_iso=5 precision={precision}", flush=True)
+    c, rho, T, rm, w = cases.heater_case()
+    c = dict(c, n_iso=5)
+    pr = _problem(c, rho, T, 12, 5, precision=precision)
+    pr.run(c["t_bottom_val"])
+    g = pr.adjoint.backward(1.0)
+    go = _oracle_grad(c, rho, T, 12, rm, w)
+    go = np.array([go[x] for x in range(c["nx"])])
+    errg = np.abs(g - go).max() / np.abs(go).max()
+    print(f"grad rel {errg:.2e}, max |grad| {np.abs(go).max():.3e}", flush=True)
+    assert np.abs(go).max() > 0
+    assert errg < (1e-10 if precision == 0 else 1e-5)
+
+
 def test_adjoint_fp64_medium_against_oracle_entries():
     """56 x 40 (several tiles), 60 steps in segments of 25: four heater
     entries against the oracle's complex-step derivatives."""
