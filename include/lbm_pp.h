@@ -106,11 +106,21 @@ typedef struct lbm_norms_t {
   double mass;        /* sum of rho over all nodes */
   double rho_mean;
   double umax;        /* max |u| */
-  double q_bottom;    /* (1/nx) sum_x lambda dT/dy at y = 0, one-sided 2nd
-                         order (Eq. pool-heat-flux); 0 unless walls */
-  double l1_rho, l2_rho, linf_rho;   /* discrete norms of rho (mean, rms, max) */
-  double l1_T, l2_T, linf_T;
-  int64_t nonfinite;  /* nodes whose rho, u or T is not finite */
+  double q_bottom;    /* wall heat flux of Eq. pool-heat-flux: (1/nx) sum_x
+                         lambda(rho) dT/dy at y = 0 with the one-sided
+                         second-order difference (-3 T0 + 4 T1 - T2)/2;
+                         ADIABATIC bottom nodes carry no flux and add 0;
+                         0 unless walls */
+  double q_heater;    /* mean of lambda dT/dy over the held (DIRICHLET)
+                         bottom nodes, the side columns included when they
+                         are held: the heater flux of a heated strip whose
+                         surroundings are adiabatic; 0 if there are none */
+  double l1_rho, l2_rho, linf_rho;   /* discrete norms of rho: mean |rho|,
+                                        rms, max |rho| */
+  double l1_T, l2_T, linf_T;         /* the same for T */
+  int64_t nonfinite;  /* nodes whose rho, u or T is not finite (left out of
+                         every other field) */
+  int64_t n_heater;   /* number of nodes averaged in q_heater */
   int64_t step;
 } lbm_norms_t;
 

@@ -503,10 +503,43 @@ class Sim:
         return self.macro()["f"]
 
     def norms(self):
+        """Global diagnostics of the state at t^n.
+
+        mass, mean, L1 (mean |.|), L2 (rms) and Linf (max |.|) of rho and T,
+        max |u|, and two bottom-wall heat fluxes built on lambda dT/dy at
+        y = 0 with the one-sided second-order difference
+        (-3 T_0 + 4 T_1 - T_2) / 2 (Eq. pool-heat-flux, sign as printed):
+          q_bottom -- (1/nx) times its sum over the bottom nodes; an
+                      adiabatic node has no flux by its condition and adds 0
+          q_heater -- its mean over the held (Dirichlet) bottom nodes: the
+                      heater of a heated strip in an adiabatic wall, the
+                      quantity a heater Nusselt number is built on
+        Nodes whose rho, u or T is not finite are counted and left out."""
         m = self.macro()
-        rho, ux, uy = m["rho"], m["ux"], m["uy"]
-        return dict(mass=float(np.real(rho.sum())), rho_mean=float(np.real(rho.mean())),
-                    umax=float(np.real(np.sqrt(ux * ux + uy * uy)).max()), step=self.n)
+        rho, ux, uy = np.real(m["rho"]), np.real(m["ux"]), np.real(m["uy"])
+        T = np.real(self.T)
+        n = rho.size
+        fin = np.isfinite(rho) & np.isfinite(T) & np.isfinite(ux) & np.isfinite(uy)
+        r, t = rho[fin], T[fin]
+        umag = np.sqrt(ux[fin] ** 2 + uy[fin] ** 2)
+        out = dict(mass=float(r.sum()), rho_mean=float(r.sum() / n),
+                   umax=float(umag.max()) if umag.size else 0.0,
+                   l1_rho=float(np.abs(r).sum() / n), l2_rho=float(np.sqrt((r * r).sum() / n)),
+                   linf_rho=float(np.abs(r).max()) if r.size else 0.0,
+                   l1_T=float(np.abs(t).sum() / n), l2_T=float(np.sqrt((t * t).sum() / n)),
+                   linf_T=float(np.abs(t).max()) if t.size else 0.0,
+                   nonfinite=int(n - np.count_nonzero(fin)), q_bottom=0.0, q_heater=0.0,
+                   n_heater=0, step=self.n)
+        if self.p.walls:
+            kind = self.tkind[0]
+            lam = self.conductivity(rho[0])
+            flux = lam * (-3.0 * T[0] + 4.0 * T[1] - T[2]) / 2.0
+            ok = fin[0] & (kind != ADIABATIC)
+            held = fin[0] & (kind == DIRICHLET)
+            out["q_bottom"] = float(flux[ok].sum() / self.p.nx)
+            out["n_heater"] = int(np.count_nonzero(held))
+            out["q_heater"] = float(flux[held].mean()) if held.any() else 0.0
+        return out
 
 
 # ---------------------------------------------------------------- helpers

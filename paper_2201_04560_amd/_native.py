@@ -33,9 +33,10 @@ class LbmParams(ctypes.Structure):
 class LbmNorms(ctypes.Structure):
     _fields_ = [
         ("mass", c_double), ("rho_mean", c_double), ("umax", c_double), ("q_bottom", c_double),
+        ("q_heater", c_double),
         ("l1_rho", c_double), ("l2_rho", c_double), ("linf_rho", c_double),
         ("l1_T", c_double), ("l2_T", c_double), ("linf_T", c_double),
-        ("nonfinite", c_int64), ("step", c_int64),
+        ("nonfinite", c_int64), ("n_heater", c_int64), ("step", c_int64),
     ]
 
 

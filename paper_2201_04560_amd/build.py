@@ -1,19 +1,28 @@
 """Build the HIP library of the package for gfx950 with hipcc (in-tree).
 
-The shared library is written next to this file; the Python binding loads
-it from there.  Building needs hipcc but no GPU.
+Each source is compiled to an object of its own (in parallel) under
+_build/ next to this file, then linked into the shared library the Python
+binding loads.  Building needs hipcc but no GPU.
 """
 import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
+OBJ = os.path.join(HERE, "_build")
 LIB_NAME = "libpp2201_lbm.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
-SOURCES = ["lbm_step.hip", "lbm_aux.hip", "lbm_runtime.cpp", "lbm_batch.cpp", "lbm_adjoint.hip", "lbm_params.cpp"]
+SOURCES = ["lbm_step.hip", "lbm_aux.hip", "lbm_runtime.cpp", "lbm_batch.cpp", "lbm_adjoint.hip",
+           "lbm_params.cpp"]
 ARCH = os.environ.get("PP2201_ARCH", "gfx950")
+FLAGS = [
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+    # float32 arithmetic is issued as scalar (non-packed) VALU instructions
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+]
 
 
 def hipcc():
@@ -23,23 +32,37 @@ def hipcc():
     return exe
 
 
-def build(verbose=False):
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB_PATH + ".tmp"
-    cmd = [
-        hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-        # float32 arithmetic is issued as scalar (non-packed) VALU instructions
-        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-        "-o", tmp,
-    ] + srcs
-    if verbose:
-        print(" ".join(cmd), flush=True)
+def _run(cmd):
     res = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in res.stderr.splitlines() if "packed-fp32-ops" not in l)
-    if res.returncode != 0:
-        raise RuntimeError(f"hipcc failed ({res.returncode}):\n{err}")
-    if verbose and err.strip():
-        print(err, file=sys.stderr)
+    return res.returncode, err
+
+
+def build(verbose=False, jobs=None):
+    os.makedirs(OBJ, exist_ok=True)
+    cc = hipcc()
+    objs, cmds = [], []
+    for s in SOURCES:
+        o = os.path.join(OBJ, os.path.splitext(s)[0] + ".o")
+        objs.append(o)
+        cmds.append([cc] + FLAGS + ["-c", "-o", o, os.path.join(CSRC, s)])
+    jobs = jobs or min(len(cmds), max(1, os.cpu_count() or 1))
+    with ThreadPoolExecutor(jobs) as ex:
+        results = list(ex.map(_run, cmds))
+    for cmd, (rc, err) in zip(cmds, results):
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        if rc != 0:
+            raise RuntimeError(f"hipcc failed ({rc}) on {cmd[-1]}:\n{err}")
+        if verbose and err.strip():
+            print(err, file=sys.stderr)
+    tmp = LIB_PATH + ".tmp"
+    link = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    if verbose:
+        print(" ".join(link), flush=True)
+    rc, err = _run(link)
+    if rc != 0:
+        raise RuntimeError(f"link failed ({rc}):\n{err}")
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
 

@@ -175,8 +175,13 @@ __global__ __launch_bounds__(256) void lbm_wall_mass_multi_kernel(const WallArgs
 
 // ---------------------------------------------------------------------
 // diagnostics over the read-out fields (float64 arrays on the device)
-// partial layout per block: [mass, sum rho^2, max rho, sum T, sum T^2,
-//  max T, max |u|, nonfinite, q_bottom]
+// partial layout per block: [mass, sum rho^2, max rho, sum |T|, sum T^2,
+//  max T, max |u|, nonfinite, wall flux over the bottom nodes that are not
+//  adiabatic, flux over the held (Dirichlet) bottom nodes, their number,
+//  sum |rho|]
+// The flux is lambda dT/dy at y = 0 with the one-sided second-order
+// difference of Eq. pool-heat-flux; an adiabatic node carries no flux by
+// its condition, so it adds nothing to the wall sum.
 // ---------------------------------------------------------------------
 __global__ __launch_bounds__(256) void lbm_norms_kernel(NormArgs A) {
   const long long N = (long long)A.nx * A.ny;
@@ -193,17 +198,24 @@ __global__ __launch_bounds__(256) void lbm_norms_kernel(NormArgs A) {
     }
     v[0] += r;
     v[1] += r * r;
+    v[11] += fabs(r);
     mx_r = fmax(mx_r, fabs(r));
-    v[3] += T;
+    v[3] += fabs(T);
     v[4] += T * T;
     mx_T = fmax(mx_T, fabs(T));
     mx_u = fmax(mx_u, sqrt(ux * ux + uy * uy));
     if (A.walls && id < A.nx) {
-      // lambda dT/dy at y = 0, one-sided second order (Eq. pool-heat-flux)
       const int x = int(id);
-      const double dT = (-3.0 * T + 4.0 * A.T[A.nx + x] - A.T[2 * A.nx + x]) * 0.5;
-      const double lam = (A.lambda_l * (r - A.rho_v) + A.lambda_v * (A.rho_l - r)) / (A.rho_l - A.rho_v);
-      v[8] += lam * dT;
+      const int kind = (A.side_dir && (x == 0 || x == A.nx - 1)) ? T_DIRICHLET : A.tk_b[x];
+      if (kind != T_ADIABATIC) {
+        const double dT = (-3.0 * T + 4.0 * A.T[A.nx + x] - A.T[2 * A.nx + x]) * 0.5;
+        const double lam = (A.lambda_l * (r - A.rho_v) + A.lambda_v * (A.rho_l - r)) / (A.rho_l - A.rho_v);
+        v[8] += lam * dT;
+        if (kind == T_DIRICHLET) {
+          v[9] += lam * dT;
+          v[10] += 1.0;
+        }
+      }
     }
   }
   __shared__ double red[256 / kLanes][kNormSlots];

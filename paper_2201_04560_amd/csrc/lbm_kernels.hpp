@@ -8,7 +8,7 @@
 
 namespace lbm {
 
-constexpr int kNormSlots = 9;
+constexpr int kNormSlots = 12;
 
 // The two-wave march addresses a row's 9 population planes with 32-bit
 // per-lane byte offsets, usable while the 9 planes span less than 4 GiB, and
@@ -104,8 +104,9 @@ struct NormArgs {
   const double* ux;
   const double* uy;
   const double* T;
+  const int32_t* tk_b;  // temperature kinds of the bottom row (per column)
   double* part;
-  int nx, ny, walls;
+  int nx, ny, walls, side_dir;
   double lambda_l, lambda_v, rho_l, rho_v;
 };
 

@@ -626,10 +626,12 @@ lbm_status lbm_norms(lbm_ctx* c, lbm_norms_t* out) {
   a.ux = stg + N;
   a.uy = stg + 2 * N;
   a.T = stg + 3 * N;
+  a.tk_b = c->tabi();
   a.part = c->red();
   a.nx = c->p.nx;
   a.ny = c->p.ny;
   a.walls = c->p.walls;
+  a.side_dir = c->p.t_side_dirichlet;
   a.lambda_l = c->p.lambda_l;
   a.lambda_v = c->p.lambda_v;
   a.rho_l = c->p.rho_l;
@@ -650,7 +652,9 @@ lbm_status lbm_norms(lbm_ctx* c, lbm_norms_t* out) {
   out->rho_mean = v[0] / n;
   out->umax = v[6];
   out->q_bottom = c->p.walls ? v[8] / c->p.nx : 0.0;
-  out->l1_rho = v[0] / n;
+  out->q_heater = v[10] > 0.0 ? v[9] / v[10] : 0.0;
+  out->n_heater = int64_t(v[10]);
+  out->l1_rho = v[11] / n;
   out->l2_rho = std::sqrt(v[1] / n);
   out->linf_rho = v[2];
   out->l1_T = v[3] / n;

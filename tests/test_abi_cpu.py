@@ -44,7 +44,7 @@ def test_struct_sizes_match_header_layout(lib):
 
     # 8 int32 + 22 double + 8 int32 + 8 double
     assert ctypes.sizeof(LbmParams) == 8 * 4 + 22 * 8 + 8 * 4 + 8 * 8
-    assert ctypes.sizeof(LbmNorms) == 10 * 8 + 2 * 8
+    assert ctypes.sizeof(LbmNorms) == 11 * 8 + 3 * 8
 
 
 def test_validation(lib):

@@ -284,6 +284,69 @@ def test_pool_walls_gravity_heater(waves):
         _compare(lat, s, 1e-10, f"pool step {s.n}")
 
 
+def _pool80(kappa=0.0):
+    eos, Tsat, rv, rl = cases.coexistence()
+    nx, ny = 80, 48
+    kb = np.full(nx, 2)
+    vb = np.full(nx, Tsat)
+    rwb = np.full(nx, 6.5)
+    kb[30:50] = 1
+    vb[30:50] = 0.95 * eos.Tc
+    rwb[30:50] = 3.44
+    c = dict(nx=nx, ny=ny, a=2.0 / 49.0, sigma=0.1103, kappa=kappa, rho_l=rl, rho_v=rv, walls=True,
+             thermal=True, gy=-3e-5, cv=5.0, lambda_l=1.95, lambda_v=0.114, rho_w_bottom=rwb,
+             rho_w_top=0.38, t_bottom_kind=kb, t_bottom_val=vb, t_top_kind=np.full(nx, 1),
+             t_top_val=np.full(nx, Tsat), **cases.wl.POOL_RATES)
+    rho, T = cases.wl.pool(nx, ny, 30.0, 2.3, rl, rv, Tsat, seed_radius=6.0, seed=1)
+    return c, rho, T
+
+
+_NORM_KEYS = ("mass", "rho_mean", "umax", "q_bottom", "q_heater", "l1_rho", "l2_rho", "linf_rho",
+              "l1_T", "l2_T", "linf_T")
+
+
+def _compare_norms(n, no, tol, what):
+    errs = {k: abs(n[k] - no[k]) / max(abs(no[k]), 1e-300) for k in _NORM_KEYS}
+    print(what, {k: f"{v:.1e}" for k, v in errs.items()}, f"q_heater={n['q_heater']:.6e}",
+          f"q_bottom={n['q_bottom']:.6e}", flush=True)
+    for k, v in errs.items():
+        assert v <= tol, (what, k, v)
+    for k in ("nonfinite", "n_heater", "step"):
+        assert n[k] == no[k], (what, k, n[k], no[k])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_norms_match_oracle(precision):
+    """Every field of lbm_norms (Eq. pool-heat-flux wall and heater fluxes,
+    mass, L1/L2/Linf of rho and T, max |u|, counts) against the oracle's
+    norms on the walls + heater + gravity pool: on the same trajectory after
+    one step, and on the library's own state after 200 steps (its closed
+    populations and T loaded into the oracle, so that only the reductions
+    are compared)."""
+    print(f"case norms pool80x48 precision={precision}", flush=True)
+    c, rho, T = _pool80()
+    s = _oracle(c, rho, None, None, T)
+    lat = _lat(c, tile_y=8, precision=precision)
+    lat.init_fields(rho, None, None, T)
+    tol = 1e-12 if precision == 0 else 1e-5
+    if precision == 0:
+        _compare_norms(lat.norms(), s.norms(), tol, "norms at init")
+        s.step(1)
+        lat.step(1)
+        _compare_norms(lat.norms(), s.norms(), 1e-11, "norms after one step")
+    lat.step(199)
+    n = lat.norms()
+    s.f = lat.populations()
+    s.T = lat.fields()[3]
+    s.n = lat.step_count
+    _compare_norms(n, s.norms(), tol, "norms on the library state at step 200")
+    assert n["n_heater"] == 20
+    assert n["q_heater"] < 0 and n["q_bottom"] < 0  # the heater heats the fluid (sign as printed)
+    # the rest of the bottom is adiabatic and carries no flux: the wall
+    # flux is the heater's share
+    assert abs(n["q_bottom"] - n["q_heater"] * 20 / 80) <= 1e-12 * abs(n["q_bottom"])
+
+
 def test_tile_shape_invariance_bitwise():
     """Without gravity the result does not depend on the tiling, the XCD
     remap or the waves per strip: identical bits."""

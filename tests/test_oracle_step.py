@@ -158,6 +158,42 @@ def test_rk2_fourier_amplification():
                                atol=1e-9 * np.abs(dT).max())
 
 
+@pytest.mark.parametrize("ux,uy", [(0.05, 0.0), (0.0, -0.04), (0.03, 0.02), (-0.06, 0.035)])
+def test_rk2_fourier_amplification_with_uniform_flow(ux, uy):
+    """Frozen uniform rho and uniform velocity u0 (so div u = 0 and the
+    pressure-work term of Eq. energy-equation vanishes), constant lambda:
+    K(T) is linear, and a Fourier mode exp(i k.x) of T is multiplied per
+    step by exactly 1 + z + z^2/2 with
+      z = -i (u0x Sx + u0y Sy) + alpha * (Laplacian symbol),
+    where Sx = sin kx (2 + cos ky)/3 is the symbol of the isotropic
+    gradient sum_i W_i phi(x + c_i) c_x (and Sy by symmetry).  The
+    imaginary part of z carries the advection term -u.grad T: its sign
+    fixes the direction the mode travels."""
+    nx, ny = 16, 12
+    kx, ky = 2 * np.pi * 3 / nx, 2 * np.pi * 2 / ny
+    rho0, cv, lam = 0.3, 5.0, 0.5
+    p = Params(nx=nx, ny=ny, a=A, rho_l=RL, rho_v=RV, thermal=True, cv=cv,
+               lambda_l=lam, lambda_v=lam)
+    s = Sim(p)
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    eps = 1e-6 * T86
+    phase = np.exp(1j * (kx * x + ky * y))
+    dT = eps * np.real(phase)
+    Tn = s.energy_update(T86 + dT, np.full((ny, nx), rho0), np.full((ny, nx), ux),
+                         np.full((ny, nx), uy))
+    alpha = lam / (rho0 * cv)
+    lap = (4 / 3) * (np.cos(kx) + np.cos(ky)) + (2 / 3) * np.cos(kx) * np.cos(ky) - 10 / 3
+    sx = np.sin(kx) * (2 + np.cos(ky)) / 3
+    sy = np.sin(ky) * (2 + np.cos(kx)) / 3
+    z = -1j * (ux * sx + uy * sy) + alpha * lap
+    expect = eps * np.real((1 + z + z * z / 2) * phase)
+    np.testing.assert_allclose(Tn - T86, expect, rtol=0, atol=1e-9 * eps)
+    # the advected part is not small against the tolerance: a reversed
+    # advection sign moves the mode by far more than the bound
+    wrong = eps * np.real((1 + np.conj(z) + np.conj(z) ** 2 / 2) * phase)
+    assert np.abs(wrong - expect).max() > 1e3 * 1e-9 * eps
+
+
 def test_shear_wave_decay_gives_mrt_viscosity():
     """Single phase above T_c, uniform density: a shear wave u_x = U sin(k y)
     decays like exp(-nu k^2 t) with nu = (1/s_nu - 1/2)/3."""
