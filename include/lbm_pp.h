@@ -297,7 +297,10 @@ void lbm_adjoint_destroy(lbm_adjoint* a);
 /* Advance ctx (initialised) by nsteps from its current state; J on the host. */
 lbm_status lbm_adjoint_forward(lbm_adjoint* a, double* J);
 /* grad_t_bottom (host, nx doubles) = dJ * dJ/dt_bottom_val.  Needs a
- * forward pass first; may be called again for another dJ. */
+ * forward pass first; may be called again for another dJ.  LBM_E_STATE if
+ * the context was stepped, re-initialised, given new boundary tables, loaded
+ * from a saved state or run in a batch since that forward pass (the gradient
+ * would belong to another trajectory). */
 lbm_status lbm_adjoint_backward(lbm_adjoint* a, double dJ, double* grad_t_bottom);
 /* Host wall-clock milliseconds of the last forward and backward passes. */
 lbm_status lbm_adjoint_timing(const lbm_adjoint* a, double* forward_ms, double* backward_ms);

@@ -32,6 +32,7 @@ class HeaterAdjoint:
               None, "lbm_adjoint_bytes")
         self._buf = torch.empty(n.value + 256, dtype=torch.uint8, device=lattice._buf.device)
         aligned = (self._buf.data_ptr() + 255) // 256 * 256
+        self.forward_id = 0  # counts forward passes; an autograd node keeps the one it recorded
         self._a = ctypes.c_void_p()
         check(lib().lbm_adjoint_create(lattice._ctx, self.nsteps, self.ckpt_every, self.rho_mid,
                                        self.width, ctypes.c_void_p(aligned), n.value,
@@ -40,6 +41,7 @@ class HeaterAdjoint:
     def forward(self):
         """Advance the lattice by nsteps from its current state; returns J."""
         J = ctypes.c_double()
+        self.forward_id += 1
         check(lib().lbm_adjoint_forward(self._a, ctypes.byref(J)), self.lattice._ctx,
               "lbm_adjoint_forward")
         return J.value
@@ -101,11 +103,16 @@ def _autograd_function():
         def forward(ctx, t_bottom, problem):
             J = problem.run(t_bottom.detach().to("cpu", torch.float64).numpy())
             ctx.problem = problem
+            ctx.forward_id = problem.adjoint.forward_id
             ctx.dev, ctx.dtype = t_bottom.device, t_bottom.dtype
             return torch.tensor(J, dtype=torch.float64, device=t_bottom.device)
 
         @staticmethod
         def backward(ctx, gJ):
+            if ctx.problem.adjoint.forward_id != ctx.forward_id:
+                raise RuntimeError("evaporated_mass: the problem ran another forward pass after "
+                                   "this one; its gradient is gone (backward each result before "
+                                   "the next forward, or use one problem per result)")
             g = ctx.problem.adjoint.backward(float(gJ))
             return torch.from_numpy(g).to(ctx.dev, ctx.dtype), None
 

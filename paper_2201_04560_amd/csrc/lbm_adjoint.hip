@@ -571,6 +571,7 @@ struct lbm_adjoint {
   int64_t start_step = 0;
   double m0 = 0;
   bool forward_done = false;
+  uint64_t gen = 0;  // the context's generation at the end of the forward pass
   double fwd_ms = 0, bwd_ms = 0;
   Fields F{};
   Geo g{};
@@ -783,6 +784,7 @@ static lbm_status adj_forward(lbm_adjoint* a, double* J) {
   lbm_ctx* c = a->c;
   if (!c->initialized) return fail(c, LBM_E_STATE, "adjoint forward before lbm_init_fields");
   const auto t0 = std::chrono::steady_clock::now();
+  a->forward_done = false;
   double* out = reinterpret_cast<double*>(a->buf + a->off_out);
   a->start_step = c->step;
   // M_l at the start: stage the current state in checkpoint 0
@@ -809,6 +811,7 @@ static lbm_status adj_forward(lbm_adjoint* a, double* J) {
   if (s != LBM_OK) return s;
   if (J) *J = a->m0 - m1;
   a->forward_done = true;
+  a->gen = c->generation;
   a->fwd_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return LBM_OK;
 }
@@ -836,6 +839,13 @@ template <class S>
 static lbm_status adj_backward(lbm_adjoint* a, double dJ, double* grad_host) {
   lbm_ctx* c = a->c;
   if (!a->forward_done) return fail(c, LBM_E_STATE, "adjoint backward before forward");
+  // the backward replays the recorded trajectory with the lattice's current
+  // boundary tables and leaves the lattice at the forward's end state: both
+  // are wrong once anything stepped, re-initialised or re-bounded it
+  if (c->generation != a->gen)
+    return fail(c, LBM_E_STATE,
+                "the lattice changed (step, init, boundary, state load or batch run) since the "
+                "adjoint forward pass: run the forward pass again");
   const auto t0 = std::chrono::steady_clock::now();
   const Geo& g = a->g;
   const int nodes = g.nx * g.ny;

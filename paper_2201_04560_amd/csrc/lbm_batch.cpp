@@ -333,6 +333,7 @@ lbm_status lbm_batch_run(lbm_batch* b, const int64_t* steps, int32_t use_graph) 
     c->pcur = st[k].pcur;
     c->npart = st[k].npart;
     c->step = st[k].step;
+    ++c->generation;
   }
   return LBM_OK;
 }

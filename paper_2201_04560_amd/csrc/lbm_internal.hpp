@@ -31,8 +31,13 @@ struct lbm_ctx {
   hipStream_t stream = nullptr;
   char* base = nullptr;
   size_t bytes = 0;
+  int device = -1;  // the GPU that holds the buffer
   int cur = 0, Tcur = 0, pcur = 0, npart = 0;
   int64_t step = 0;
+  // bumped by every call that changes the state or the boundary tables
+  // (step, init, boundary, state load, batch run): an adjoint backward
+  // checks that nothing changed since its forward pass
+  uint64_t generation = 0;
   bool initialized = false;
   std::vector<double> rw_b, rw_t, tv_b, tv_t;
   std::vector<int32_t> tk_b, tk_t;
@@ -77,7 +82,18 @@ struct lbm_ctx {
 
 
 namespace lbm {
+// workgroups of the diagnostics reduction (grid-stride over the lattice)
+constexpr int kNormBlocks = 512;
+
 lbm_status fail(lbm_ctx* c, lbm_status s, const std::string& msg);
+// read-out kernel: rho, u, T (and/or populations) of the current step into
+// the given device arrays (the idle population buffer serves as staging)
+lbm_status run_macro(lbm_ctx* c, double* o_rho, double* o_ux, double* o_uy, double* o_T, double* o_f,
+                     int f_first, int f_count);
+// arguments of the diagnostics kernel over the fields staged at stg, its
+// per-workgroup partial sums going to part; and its workgroup count
+NormArgs norm_args(const lbm_ctx* c, const double* stg, double* part);
+int norm_blocks(const lbm_ctx* c);
 LaunchStep step_args(lbm_ctx* c);
 LaunchWall wall_args(lbm_ctx* c, const LaunchStep& L);
 void make_layout(const lbm_params& p, Layout& L);

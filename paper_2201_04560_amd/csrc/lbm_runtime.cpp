@@ -18,8 +18,7 @@ using namespace lbm;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr uint64_t kStateMagic = 0x314D424C50504E42ull;  // "BNPPLBM1"
-constexpr int kNormBlocks = 512;
+constexpr uint64_t kStateMagic = 0x324D424C50504E42ull;  // "BNPPLBM2"
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -264,6 +263,15 @@ lbm_status lbm_create(const lbm_params* p, void* dev_buf, size_t bytes, void* hi
       (void)hipGetLastError();  // keep the device-independent default
     }
   }
+  {
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, dev_buf) == hipSuccess) {
+      c->device = attr.device;
+    } else {
+      (void)hipGetLastError();
+      if (hipGetDevice(&c->device) != hipSuccess) c->device = -1;
+    }
+  }
   c->ph = make_phys(*p);
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->base = static_cast<char*>(dev_buf);
@@ -316,6 +324,7 @@ lbm_status lbm_set_boundary(lbm_ctx* c, const double* rho_w_bottom, const double
                             const int32_t* t_bottom_kind, const double* t_bottom_val,
                             const int32_t* t_top_kind, const double* t_top_val) {
   if (!c) return LBM_E_INVAL;
+  ++c->generation;  // even a rejected call may leave some tables replaced
   const int nx = c->p.nx;
   auto kind_ok = [&](const int32_t* k) {
     if (!k) return true;
@@ -409,6 +418,7 @@ lbm_status lbm_init_fields(lbm_ctx* c, const double* rho, const double* ux, cons
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->npart = init_blocks(nx, ny);
   c->step = 0;
+  ++c->generation;
   c->initialized = true;
   return LBM_OK;
 }
@@ -521,6 +531,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
       c->npart = c->L.nblocks;
     }
     ++c->step;
+    ++c->generation;
   }
   HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
   c->timed = true;
@@ -559,9 +570,11 @@ lbm_status lbm_last_step_time(lbm_ctx* c, double* total_ms) {
   return LBM_OK;
 }
 
+}  // extern "C"
+
 // read-out kernel into the idle population buffer
-static lbm_status run_macro(lbm_ctx* c, double* o_rho, double* o_ux, double* o_uy, double* o_T,
-                            double* o_f, int f_first, int f_count) {
+lbm_status lbm::run_macro(lbm_ctx* c, double* o_rho, double* o_ux, double* o_uy, double* o_T,
+                          double* o_f, int f_first, int f_count) {
   LaunchStep L = step_args(c);
   L.fout = nullptr;
   L.Tout = nullptr;
@@ -581,6 +594,8 @@ static lbm_status run_macro(lbm_ctx* c, double* o_rho, double* o_ux, double* o_u
   HIP_TRY(c, launch_macro(L, c->stream));
   return LBM_OK;
 }
+
+extern "C" {
 
 lbm_status lbm_read_fields(lbm_ctx* c, double* rho, double* ux, double* uy, double* T) {
   if (!c) return LBM_E_INVAL;
@@ -614,20 +629,17 @@ lbm_status lbm_read_populations(lbm_ctx* c, double* f) {
   return check_err(c);
 }
 
-lbm_status lbm_norms(lbm_ctx* c, lbm_norms_t* out) {
-  if (!c || !out) return LBM_E_INVAL;
-  if (!c->initialized) return fail(c, LBM_E_STATE, "norms before init");
+}  // extern "C"
+
+NormArgs lbm::norm_args(const lbm_ctx* c, const double* stg, double* part) {
   const size_t N = size_t(c->p.nx) * c->p.ny;
-  double* stg = static_cast<double*>(c->f(1 - c->cur));
-  lbm_status s = run_macro(c, stg, stg + N, stg + 2 * N, stg + 3 * N, nullptr, 0, 0);
-  if (s != LBM_OK) return s;
   NormArgs a{};
   a.rho = stg;
   a.ux = stg + N;
   a.uy = stg + 2 * N;
   a.T = stg + 3 * N;
   a.tk_b = c->tabi();
-  a.part = c->red();
+  a.part = part;
   a.nx = c->p.nx;
   a.ny = c->p.ny;
   a.walls = c->p.walls;
@@ -636,8 +648,25 @@ lbm_status lbm_norms(lbm_ctx* c, lbm_norms_t* out) {
   a.lambda_v = c->p.lambda_v;
   a.rho_l = c->p.rho_l;
   a.rho_v = c->p.rho_v;
-  const int nb = int(std::min<size_t>(kNormBlocks, (N + 255) / 256));
-  HIP_TRY(c, launch_norms(a, nb, c->stream));
+  return a;
+}
+
+int lbm::norm_blocks(const lbm_ctx* c) {
+  const size_t N = size_t(c->p.nx) * c->p.ny;
+  return int(std::min<size_t>(kNormBlocks, (N + 255) / 256));
+}
+
+extern "C" {
+
+lbm_status lbm_norms(lbm_ctx* c, lbm_norms_t* out) {
+  if (!c || !out) return LBM_E_INVAL;
+  if (!c->initialized) return fail(c, LBM_E_STATE, "norms before init");
+  const size_t N = size_t(c->p.nx) * c->p.ny;
+  double* stg = static_cast<double*>(c->f(1 - c->cur));
+  lbm_status s = run_macro(c, stg, stg + N, stg + 2 * N, stg + 3 * N, nullptr, 0, 0);
+  if (s != LBM_OK) return s;
+  const int nb = norm_blocks(c);
+  HIP_TRY(c, launch_norms(norm_args(c, stg, c->red()), nb, c->stream));
   std::vector<double> part(size_t(nb) * kNormSlots);
   HIP_TRY(c, hipMemcpyAsync(part.data(), c->red(), part.size() * 8, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -679,7 +708,25 @@ struct StateHeader {
   int64_t step;
   int32_t nx, ny, precision, npart;
   uint64_t fbytes, tbytes, pbytes;
+  uint64_t phash;  // hash of the parameters that shape the state (all but the launch choices)
 };
+
+// FNV-1a over the parameter block with the launch-only fields (strip height,
+// waves per strip, XCD remap) cleared: a state saved under other physics,
+// walls or sizes does not load
+uint64_t params_hash(const lbm_params& p0) {
+  lbm_params p = p0;
+  p.tile_y = 0;
+  p.strip_waves = 0;
+  p.xcd_remap = 0;
+  uint64_t h = 1469598103934665603ull;
+  const unsigned char* b = reinterpret_cast<const unsigned char*>(&p);
+  for (size_t i = 0; i < sizeof p; ++i) {
+    h ^= b[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
 
 lbm_status lbm_state_bytes(const lbm_ctx* c, size_t* bytes) {
   if (!c || !bytes) return LBM_E_INVAL;
@@ -705,6 +752,7 @@ lbm_status lbm_save_state(lbm_ctx* c, void* host, size_t bytes) {
   h.fbytes = size_t(9 * c->L.plane) * c->L.elem;
   h.tbytes = size_t(c->L.pitch) * c->p.ny * c->L.elem;
   h.pbytes = size_t(c->L.part_cap) * 8;
+  h.phash = params_hash(c->p);
   char* o = static_cast<char*>(host);
   std::memcpy(o, &h, sizeof h);
   o += sizeof h;
@@ -724,8 +772,10 @@ lbm_status lbm_load_state(lbm_ctx* c, const void* host, size_t bytes) {
   StateHeader h;
   std::memcpy(&h, host, sizeof h);
   if (h.magic != kStateMagic || h.nx != c->p.nx || h.ny != c->p.ny || h.precision != c->p.precision ||
-      h.fbytes != size_t(9 * c->L.plane) * c->L.elem)
-    return fail(c, LBM_E_INVAL, "state does not match this context");
+      h.fbytes != size_t(9 * c->L.plane) * c->L.elem ||
+      h.tbytes != size_t(c->L.pitch) * c->p.ny * c->L.elem || h.pbytes != size_t(c->L.part_cap) * 8 ||
+      h.npart < 0 || h.npart > c->L.part_cap || h.phash != params_hash(c->p))
+    return fail(c, LBM_E_INVAL, "state does not match this context (size, storage or parameters)");
   lbm_status s = upload_tables(c);
   if (s != LBM_OK) return s;
   const char* i = static_cast<const char*>(host) + sizeof h;
@@ -741,6 +791,7 @@ lbm_status lbm_load_state(lbm_ctx* c, const void* host, size_t bytes) {
   c->npart = h.npart;
   c->step = h.step;
   c->initialized = true;
+  ++c->generation;
   return LBM_OK;
 }
 

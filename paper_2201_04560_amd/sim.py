@@ -88,7 +88,11 @@ class Lattice:
             if v is None:
                 return None
             v = np.asarray(v, dtype=dt)
-            return np.ascontiguousarray(np.full(nx, v, dtype=dt) if v.ndim == 0 else v)
+            if v.ndim == 0:
+                return np.full(nx, v, dtype=dt)
+            if v.shape != (nx,):
+                raise ValueError(f"boundary column arrays need nx = {nx} entries, got shape {v.shape}")
+            return np.ascontiguousarray(v)
 
         arrs = [col(rho_w_bottom, np.float64), col(rho_w_top, np.float64),
                 col(t_bottom_kind, np.int32), col(t_bottom_val, np.float64),

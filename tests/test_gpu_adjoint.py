@@ -137,6 +137,68 @@ def test_autograd_function():
     assert np.abs(tb.grad.numpy() - 3.0 * go).max() <= 1e-10 * np.abs(3.0 * go).max()
 
 
+@pytest.mark.parametrize("nsteps", [1, 2])
+def test_adjoint_dot_product_one_step(nsteps):
+    """Adjoint identity of the heater-to-J map over one (and two) steps:
+    <grad J, v> from the library's reverse pass equals the oracle's
+    complex-step directional derivative dJ/dTb . v (exact to rounding) for
+    random directions v, to 1e-12 of |grad J| |v|."""
+    print(f"case adjoint dot product nsteps={nsteps}", flush=True)
+    c, rho, T, rm, w = cases.heater_case(20, 16, r=4.0, cy=5.0, seed=11)
+    pr = _problem(c, rho, T, nsteps, 1)
+    pr.run(c["t_bottom_val"])
+    g = pr.adjoint.backward(1.0)
+    rng = np.random.default_rng(5 + nsteps)
+    for _ in range(3):
+        v = rng.standard_normal(c["nx"])
+        dd = oadj.heater_directional_derivative(cases.oracle_params(c), rho, T, nsteps, rm, w, v)
+        print(f"<g, v> {g @ v:.15e} oracle {dd:.15e}", flush=True)
+        assert abs(g @ v - dd) <= 1e-12 * np.linalg.norm(g) * np.linalg.norm(v)
+
+
+def test_adjoint_backward_refuses_a_changed_lattice():
+    """A backward after the lattice was stepped, re-initialised or given new
+    boundary tables would replay another trajectory: LBM_E_STATE; a new
+    forward pass makes it valid again."""
+    print("case adjoint stale backward", flush=True)
+    from paper_2201_04560_amd import LbmError
+
+    c, rho, T, rm, w = cases.heater_case()
+    pr = _problem(c, rho, T, 12, 5)
+    pr.run(c["t_bottom_val"])
+    g0 = pr.adjoint.backward(1.0)
+    pr.lattice.step(1)
+    with pytest.raises(LbmError) as ei:
+        pr.adjoint.backward(1.0)
+    assert ei.value.status == 4
+    pr.run(c["t_bottom_val"])
+    assert np.array_equal(pr.adjoint.backward(1.0), g0)
+    pr.lattice.set_boundary(t_bottom_val=c["t_bottom_val"] * 1.001)
+    with pytest.raises(LbmError):
+        pr.adjoint.backward(1.0)
+
+
+def test_autograd_refuses_a_stale_node():
+    """Two forward passes of one problem, then the first one's backward:
+    its recorded trajectory is gone, so autograd raises instead of returning
+    the second trajectory's gradient."""
+    print("case adjoint autograd stale", flush=True)
+    import torch
+
+    from paper_2201_04560_amd import evaporated_mass
+
+    c, rho, T, rm, w = cases.heater_case()
+    pr = _problem(c, rho, T, 12, 5)
+    t1 = torch.tensor(c["t_bottom_val"], dtype=torch.float64, requires_grad=True)
+    t2 = torch.tensor(c["t_bottom_val"] * 1.002, dtype=torch.float64, requires_grad=True)
+    J1 = evaporated_mass(t1, pr)
+    J2 = evaporated_mass(t2, pr)
+    with pytest.raises(RuntimeError, match="another forward pass"):
+        J1.backward()
+    J2.backward()
+    assert torch.isfinite(t2.grad).all()
+
+
 def test_adjoint_fp32_storage_tracks_fp64():
     """Float32 shifted storage: the forward and its checkpoints in float32,
     the adjoint arithmetic in float64 at that trajectory (parity unpinned:

@@ -377,6 +377,37 @@ def test_checkpoint_restart_bitwise():
     assert np.array_equal(a, lat.populations())
 
 
+def test_load_state_rejects_foreign_states():
+    """A state saved on a lattice of other walls or physics (same size and
+    storage) is refused with LBM_E_INVAL and leaves the context as it was;
+    boundary columns of the wrong length are refused by the binding."""
+    print("case load_state validation", flush=True)
+    from paper_2201_04560_amd import LbmError
+
+    c, rho, ux, uy, T = cases.random_tiny(70, 30, seed=9, walls=True, thermal=True, gy=-1e-3)
+    walls = _lat(c, tile_y=8)
+    walls.init_fields(rho, ux, uy, T)
+    walls.step(3)
+    st = walls.save_state()
+    c2 = dict(c, walls=False)
+    per = _lat(c2, tile_y=8)
+    per.init_fields(rho, ux, uy, T)
+    per.step(2)
+    before = per.populations()
+    with pytest.raises(LbmError) as ei:
+        per.load_state(st)
+    assert ei.value.status == 1
+    assert per.step_count == 2 and np.array_equal(before, per.populations())
+    other = _lat(dict(c, kappa=0.25), tile_y=8)
+    other.init_fields(rho, ux, uy, T)
+    with pytest.raises(LbmError):
+        other.load_state(st)
+    walls.load_state(st)  # its own state still loads
+    assert walls.step_count == 3
+    with pytest.raises(ValueError):
+        walls.set_boundary(t_bottom_val=np.full(c["nx"] - 1, 0.06))
+
+
 def test_domain_error_is_reported():
     print("case domain error", flush=True)
     from paper_2201_04560_amd import LbmError
