@@ -177,6 +177,22 @@ lbm_status lbm_read_populations(lbm_ctx* ctx, double* f);
 /* Global diagnostics (fixed-order float64 reductions).  Synchronises. */
 lbm_status lbm_norms(lbm_ctx* ctx, lbm_norms_t* out);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the diagnostics of
+ * lbm_norms() written as one lbm_norms_t into device memory (dev_out,
+ * 8-byte aligned, caller-owned), enqueued on the context stream without
+ * synchronising and without any host or device allocation.  Its reduction
+ * keeps the per-workgroup partial sums in a fixed library array of 48 KiB
+ * per GPU (512 workgroups x 12 sums; the reduction never uses more, so every
+ * lattice size fits), held until the process ends; the read-out stages
+ * rho, u, T in the context's idle population buffer, as lbm_norms() does.
+ * The values equal lbm_norms()'s (same partial sums, same final order);
+ * `step` is the host's count when the call is enqueued.  Calls that overlap
+ * on one GPU (contexts on different streams) share that array and race:
+ * order them on one stream or by events.  Device errors stay sticky and are
+ * reported by the next synchronising call. */
+lbm_status lbm_norms_device(lbm_ctx* ctx, lbm_norms_t* dev_out);
+
 /* Checkpoint: raw storage of the populations, T and the step counter. */
 lbm_status lbm_state_bytes(const lbm_ctx* ctx, size_t* bytes);
 lbm_status lbm_save_state(lbm_ctx* ctx, void* host, size_t bytes);

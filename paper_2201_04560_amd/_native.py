@@ -62,6 +62,7 @@ SIGNATURES = [
     ("lbm_read_fields", c_int32, [c_void_p, _DP, _DP, _DP, _DP]),
     ("lbm_read_populations", c_int32, [c_void_p, _DP]),
     ("lbm_norms", c_int32, [c_void_p, P(LbmNorms)]),
+    ("lbm_norms_device", c_int32, [c_void_p, c_void_p]),
     ("lbm_state_bytes", c_int32, [c_void_p, P(c_size_t)]),
     ("lbm_save_state", c_int32, [c_void_p, c_void_p, c_size_t]),
     ("lbm_load_state", c_int32, [c_void_p, c_void_p, c_size_t]),

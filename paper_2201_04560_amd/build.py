@@ -16,7 +16,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB_NAME = "libpp2201_lbm.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
 SOURCES = ["lbm_step.hip", "lbm_aux.hip", "lbm_runtime.cpp", "lbm_batch.cpp", "lbm_adjoint.hip",
-           "lbm_params.cpp"]
+           "lbm_params.cpp", "lbm_static.hip"]
 ARCH = os.environ.get("PP2201_ARCH", "gfx950")
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
