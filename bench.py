@@ -1,20 +1,21 @@
 #!/usr/bin/env python3
 """Throughput of the fused pseudopotential-LBM step on one MI355X.
 
-Workload (the metric's configuration): droplet vaporisation on a 512 x 512
-periodic lattice -- a liquid disk of radius 60 (seed-jittered by +-0.5) at
-T_sat = 0.86 T_c in vapour held at 0.95 T_c on the outer ring, Peng-Robinson
-EOS a = 2/49, b = 2/21, sigma = kappa = 0.1, all MRT rates 1.25, c_v = 6,
-lambda = 2/3, no gravity, energy equation on from step 0.  The float32
-shifted-storage step is timed, then the float64 plain step on the same
-input; both run warmup + steps time steps and the final rho / T of the
-float32 run are compared with the float64 run.
+Workload (the metric's configuration): droplet vaporisation on 512 x 512
+periodic lattices, seeds 0-3 -- a liquid disk of radius 60 (seed-jittered by
++-0.5) at T_sat = 0.86 T_c in vapour held at 0.95 T_c on the outer ring,
+Peng-Robinson EOS a = 2/49, b = 2/21, sigma = kappa = 0.1, all MRT rates
+1.25, c_v = 6, lambda = 2/3, no gravity, energy equation on from step 0.  A
+step advances the four seeds by one time step: the float32 shifted-storage
+step runs them in one batched launch per step (graph-replayed), the float64
+plain step one lattice after another.  The float32 accuracy is stated after
+the configuration's 20,000 steps on all four seeds, whatever --steps is.
 
 Prints ONE JSON line (last line of stdout) with the metric, the roofline
-of the step kernel (HIP events around every launch in the timed region),
-the float64 comparison, an HBM-sized run (4096 x 4096 pool boiling
-physics: walls, heater, gravity) and the float64 oracle timed on the host
-(one core, a bounded number of steps of the same workload).
+of the step kernel (HIP events around the timed launches), the float64
+comparison, the single-lattice figures, an HBM-sized run (4096 x 4096 pool
+boiling physics: walls, heater, gravity), the refinement ladder, the
+adjoint, and the float64 oracle timed on one pinned host core.
 """
 import argparse
 import hashlib
@@ -125,6 +126,146 @@ def run_lattice(case, precision, warmup, steps, want_fields=True, tile_y=0, tune
     return out
 
 
+SEEDS = (0, 1, 2, 3)
+
+
+def vap_lattices(precision, seeds=SEEDS, tile_y=0, strip_waves=0, n=512, **over):
+    """One initialised lattice of the vaporisation workload per seed."""
+    from paper_2201_04560_amd import Lattice, make_params
+
+    out = []
+    for sd in seeds:
+        nx, ny, kw, bnd, rho, T = vaporisation_case(n, seed=sd)
+        lat = Lattice(make_params(nx, ny, precision=precision, tile_y=tile_y,
+                                  strip_waves=strip_waves, **dict(kw, **over)))
+        lat.set_boundary(**bnd)
+        lat.init_fields(rho, None, None, T)
+        out.append(lat)
+    return out
+
+
+def tune_vap_batch(tune, precision, seeds=SEEDS):
+    """(strip height, waves per strip) of the batched launch of the seeds,
+    from the tile cache or its autotuner (throwaway lattices)."""
+    if tune is None:
+        return 5, 2
+    return tune.tune_batch(lambda: vap_lattices(precision, seeds), device=device_key(),
+                           candidates=(4, 5, 6, 8, 10, 12, 13, 16, 20, 24, 32), steps=20,
+                           waves=(1, 2), with_waves=True)
+
+
+def run_vap_batch(precision, warmup, steps, tile_y, waves, seeds=SEEDS, want_fields=True):
+    """The seeds advanced together: one multi-lattice launch per step,
+    repeated launch pairs replayed from a captured graph.  Host wall clock
+    around the timed run; the batch's HIP events (recorded on its stream
+    around the same launches) give the kernel's average launch duration."""
+    import torch
+
+    from paper_2201_04560_amd import Batch
+
+    lats = vap_lattices(precision, seeds, tile_y, waves)
+    b = Batch(lats)
+    n = len(lats)
+    if warmup:
+        b.run([warmup] * n)
+    # tables and graphs of the timed schedule set up ahead (no launch)
+    b.prepare([steps] * n)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run([steps] * n)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms, launches, graphs = b.last_time()
+    out = dict(wall_s=wall, ev_ms=ms, kernel_ms_avg=ms / max(launches, 1), launches=launches,
+               graph_launches=graphs, tile_y=lats[0].tile_y, strip_waves=lats[0].strip_waves)
+    if want_fields:
+        out["fields"] = [lat.fields() for lat in lats]
+        out["norms"] = [lat.norms() for lat in lats]
+        out["populations0"] = lats[0].populations()
+    b.close()
+    for lat in lats:
+        lat.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_vap_plain(precision, warmup, steps, seeds=SEEDS, tile_y=0, waves=0, want_fields=True):
+    """The plain step: the seeds one lattice after another, one launch per
+    step each (the library's default strip height and waves per strip)."""
+    import torch
+
+    lats = vap_lattices(precision, seeds, tile_y, waves)
+    for lat in lats:
+        if warmup:
+            lat.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for lat in lats:
+        lat.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev = sum(lat.last_step_ms() for lat in lats)
+    out = dict(wall_s=wall, ev_ms=ev, kernel_ms_avg=ev / (steps * len(lats)), launches=steps * len(lats),
+               tile_y=lats[0].tile_y, strip_waves=lats[0].strip_waves)
+    if want_fields:
+        out["fields"] = [lat.fields() for lat in lats]
+        out["norms"] = [lat.norms() for lat in lats]
+    for lat in lats:
+        lat.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def batch_bitwise_vs_solo(res, precision, nsteps, seed=SEEDS[0]):
+    """The batched run's first lattice against the same seed stepped alone
+    (lbm_step, same strip height and waves): identical bits expected."""
+    import torch
+
+    lat = vap_lattices(precision, (seed,), res["tile_y"], res["strip_waves"])[0]
+    lat.step(nsteps)
+    same = bool(np.array_equal(lat.populations(), res["populations0"]))
+    lat.close()
+    torch.cuda.empty_cache()
+    return same
+
+
+def accuracy_20k(steps, tune, seeds=SEEDS):
+    """Float32 shifted storage against the float64 step after the
+    configuration's length on every seed: max relative rho / T deviation,
+    mass, liquid fraction, droplet radius and coexistence densities; the
+    float32 storage with rho_ref = the mean density on seed 0."""
+    ty32, w32 = tune_vap_batch(tune, 1, seeds)
+    t0 = time.perf_counter()
+    r32 = run_vap_batch(1, 0, steps, ty32, w32, seeds)
+    r64 = run_vap_batch(0, 0, steps, 5, 2, seeds)
+    nx, ny, kw, bnd, rho0, T0 = vaporisation_case(512, seed=seeds[0])
+    rl, rv = kw["rho_l"], kw["rho_v"]
+    mid = 0.5 * (rl + rv)
+    per = []
+    for k, sd in enumerate(seeds):
+        a, _, _, Ta = r32["fields"][k]
+        c, _, _, Tc = r64["fields"][k]
+        per.append({"seed": sd, "rho_max_rel": rel_err(a, c), "T_max_rel": rel_err(Ta, Tc),
+                    "mass_rel": abs(r32["norms"][k]["mass"] / r64["norms"][k]["mass"] - 1),
+                    "liquid_fraction_fp32": float((a > mid).mean()),
+                    "liquid_fraction_fp64": float((c > mid).mean()),
+                    "fp32": droplet_stats(a, rl, rv), "fp64": droplet_stats(c, rl, rv)})
+    mean_ref = float(rho0.mean())
+    lm = vap_lattices(1, (seeds[0],), 5, 2, rho_ref=mean_ref)[0]
+    lm.step(steps)
+    rm, _, _, Tm = lm.fields()
+    lm.close()
+    c, _, _, Tc = r64["fields"][0]
+    return {"after_steps": steps, "seeds": list(seeds),
+            "rho_max_rel": max(p["rho_max_rel"] for p in per),
+            "T_max_rel": max(p["T_max_rel"] for p in per),
+            "mass_rel": max(p["mass_rel"] for p in per),
+            "per_seed": per,
+            "fp32_rho_ref_mean_seed0": {"rho_ref": mean_ref, "rho_max_rel": rel_err(rm, c),
+                                        "T_max_rel": rel_err(Tm, Tc), **droplet_stats(rm, rl, rv)},
+            "wall_s": round(time.perf_counter() - t0, 2)}
+
+
 def roofline(fp32, nodes, kernel_ms, traffic):
     b = alg_bytes_per_node(fp32) * nodes
     achieved = b / (kernel_ms * 1e-3) / 1e9
@@ -154,7 +295,8 @@ def measured_traffic(key, tile_y, waves):
 
 KERNEL_SOURCES = ["paper_2201_04560_amd/csrc/lbm_step.hip", "paper_2201_04560_amd/csrc/lbm_device.hpp",
                   "paper_2201_04560_amd/csrc/lbm_kernels.hpp"]
-PROFILE_NODES = {"vaporisation512": 512 * 512, "pool4096": 4096 * 4096}
+PROFILE_NODES = {"vaporisation512": 512 * 512, "vaporisation512x4": 4 * 512 * 512,
+                 "pool4096": 4096 * 4096}
 
 
 def write_traffic(pmc_dir, copy_mib):
@@ -241,8 +383,29 @@ def with_copy_fraction(rl, copy_gbs):
     return rl
 
 
+def host_cpu():
+    """Host CPU model and the logical CPUs this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count() or 0
+    return model, os.cpu_count() or 0, avail
+
+
 def cpu_baseline(case, budget_s=15.0):
-    """The float64 oracle on the host, one core, a bounded number of steps."""
+    """The float64 oracle on the host: the calling thread pinned to one core
+    (os.sched_setaffinity on this thread; the process has already started
+    the GPU runtime, so it is not re-launched under taskset) and BLAS thread
+    pools limited to one thread, a bounded number of steps."""
     try:
         from threadpoolctl import threadpool_limits
     except ImportError:
@@ -257,21 +420,36 @@ def cpu_baseline(case, budget_s=15.0):
                t_top_val=bnd["t_top_val"], **{k: kw[k] for k in keys})
     import contextlib
 
+    model, ncpu, avail = host_cpu()
+    prev = None
+    core = None
+    try:
+        prev = os.sched_getaffinity(0)
+        core = min(prev)
+        os.sched_setaffinity(0, {core})
+    except (AttributeError, OSError):
+        prev = None
     lim = threadpool_limits(limits=1) if threadpool_limits else contextlib.nullcontext()
-    with lim:
-        s = Sim(p)
-        s.init_fields(rho, None, None, T)
-        t0 = time.perf_counter()
-        s.step(2)
-        per = (time.perf_counter() - t0) / 2
-        n = max(3, int(budget_s / per))
-        t0 = time.perf_counter()
-        s.step(n)
-        dt = time.perf_counter() - t0
+    try:
+        with lim:
+            s = Sim(p)
+            s.init_fields(rho, None, None, T)
+            t0 = time.perf_counter()
+            s.step(2)
+            per = (time.perf_counter() - t0) / 2
+            n = max(3, int(budget_s / per))
+            t0 = time.perf_counter()
+            s.step(n)
+            dt = time.perf_counter() - t0
+    finally:
+        if prev is not None:
+            os.sched_setaffinity(0, prev)
+    pinned = f"pinned to logical CPU {core}" if core is not None else "not pinned"
     return {"value": round(nx * ny * n / dt / 1e6, 4), "unit": "MLUPS", "cores": 1,
             "kind": "oracle",
-            "sample": f"{nx}x{ny} droplet vaporisation, {n} float64 oracle steps after 2 untimed, "
-                      f"{dt:.1f} s on one host core (BLAS threads limited to 1)"}
+            "sample": f"{nx}x{ny} droplet vaporisation (seed 0), {n} float64 oracle steps after 2 "
+                      f"untimed, {dt:.1f} s on one host core ({pinned}, BLAS threads limited to 1)",
+            "host_cpu_model": model, "host_nproc": ncpu, "host_cpus_available": avail}
 
 
 def ladder_case(k, seed, precision, steps0):
@@ -289,10 +467,15 @@ def ladder_case(k, seed, precision, steps0):
 
 
 def ladder_bench(steps0, levels=(0, 1, 2, 3), seeds=(0, 1, 2, 3), tile_cache=None):
-    """16 grids (4 meshes x 4 seeds): float32 shifted storage in one batched,
-    graph-replayed launch per step with autotuned strip heights, against the
-    plain float64 step one launch per step per grid; both advance mesh k by
-    steps0 4^k steps (the same physical time)."""
+    """16 grids (4 meshes x 4 seeds), mesh k advanced by steps0 4^k steps
+    (the same physical time), four ways: float32 shifted storage in one
+    batched, graph-replayed launch per step (strip height and waves per
+    strip tuned per mesh on its seeds' batched launch); float32 one grid at a
+    time (the batching gain at equal precision); the plain float64 step one
+    grid at a time; and, on the finest mesh, a float64 batch started from the
+    float64 initial state perturbed by one ulp, whose drift from the float64
+    run is the trajectory's own sensitivity (nucleation) against which the
+    float32 deviation is read."""
     import torch
 
     from paper_2201_04560_amd import Batch, Lattice
@@ -302,10 +485,14 @@ def ladder_bench(steps0, levels=(0, 1, 2, 3), seeds=(0, 1, 2, 3), tile_cache=Non
     dev = device_key()
     specs = [(k, sd) for k in levels for sd in seeds]
 
-    def build(precision):
+    def build(precision, only=None, perturb=False):
         lats, steps = [], []
         for k, sd in specs:
+            if only is not None and k != only:
+                continue
             L, rho, T = ladder_case(k, sd, precision, steps0)
+            if perturb:
+                rho = np.nextafter(rho, np.inf)
             lat = Lattice(L["params"])
             lat.set_boundary(**L["boundary"])
             lat.init_fields(rho, None, None, T)
@@ -314,68 +501,94 @@ def ladder_bench(steps0, levels=(0, 1, 2, 3), seeds=(0, 1, 2, 3), tile_cache=Non
         return lats, steps
 
     def make(k):
-        out = []
-        for sd in seeds:
-            L, rho, T = ladder_case(k, sd, 1, steps0)
-            lat = Lattice(L["params"])
-            lat.set_boundary(**L["boundary"])
-            lat.init_fields(rho, None, None, T)
-            out.append(lat)
-        return out
+        return build(1, only=k)[0]
 
-    # strip height per mesh, tuned on the batched launch of that mesh's seeds
-    # (one wave per strip), which is what runs once the coarser meshes are done
-    tiles = {k: cache.tune_batch(lambda k=k: make(k), device=dev) for k in levels}
+    def timed_batch(lats, steps):
+        b = Batch(lats)
+        b.run([2] * len(lats))  # warm-up: graph instantiation path and caches
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.run(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        rec = b.last_time()
+        b.close()
+        return wall, rec
+
+    def timed_plain(lats, steps):
+        for lat in lats:
+            lat.step(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for lat, n in zip(lats, steps):
+            lat.step(n)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    tiles = {k: cache.tune_batch(lambda k=k: make(k), device=dev, waves=(1, 2), with_waves=True)
+             for k in levels}
     lats32, steps = build(1)
     for (k, sd), lat in zip(specs, lats32):
-        lat.tile_y = tiles[k]
+        lat.tile_y, lat.strip_waves = tiles[k]
     log(f"bench: ladder tiles {tiles}, steps {sorted(set(steps))}")
-    b = Batch(lats32)
-    b.run([2] * len(lats32))  # warm-up: graph instantiation path and caches
-    torch.cuda.synchronize()
-    # the warm-up advanced every grid by 2 steps: the fp64 run does the same
-    t0 = time.perf_counter()
-    b.run(steps)
-    torch.cuda.synchronize()
-    t32 = time.perf_counter() - t0
-    ms32, launches, graphs = b.last_time()
+    t32, (ms32, launches, graphs) = timed_batch(lats32, steps)
+    lats32p, _ = build(1)
+    t32p = timed_plain(lats32p, steps)
     lats64, _ = build(0)
-    for lat in lats64:
-        lat.step(2)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for lat, n in zip(lats64, steps):
-        lat.step(n)
-    torch.cuda.synchronize()
-    t64 = time.perf_counter() - t0
+    t64 = timed_plain(lats64, steps)
     lu = sum(l.nx * l.ny * n for l, n in zip(lats32, steps))
     per_level = {}
-    for (k, sd), a, c in zip(specs, lats32, lats64):
+    for (k, sd), a, c, ap in zip(specs, lats32, lats64, lats32p):
         r32, _, _, T32 = a.fields()
         r64, _, _, T64 = c.fields()
         e = per_level.setdefault(k, {"grid": f"{a.nx}x{a.ny}", "steps": steps[specs.index((k, sd))],
-                                     "tile_y": tiles[k], "rho_max_rel": 0.0, "T_max_rel": 0.0,
-                                     "kappa": None})
+                                     "tile_y": tiles[k][0], "strip_waves": tiles[k][1],
+                                     "rho_max_rel": 0.0, "T_max_rel": 0.0, "kappa": None,
+                                     "fp32_batched_vs_per_grid_rho_max_rel": 0.0})
         e["rho_max_rel"] = max(e["rho_max_rel"], rel_err(r32, r64))
         e["T_max_rel"] = max(e["T_max_rel"], rel_err(T32, T64))
+        # same arithmetic; with gravity the order of the mean-density partial
+        # sums follows the strip height, which differs between the two runs
+        e["fp32_batched_vs_per_grid_rho_max_rel"] = max(e["fp32_batched_vs_per_grid_rho_max_rel"],
+                                                        rel_err(r32, ap.fields()[0]))
     for k in per_level:
         from paper_2201_04560_amd.ladder import pool_level
 
         lv = pool_level(k, steps0=steps0)["level"]
         per_level[k].update(a=lv["a"], sigma=round(lv["sigma"], 6), kappa=round(lv["kappa"], 6),
                             gy=lv["gy"])
-    b.close()
-    for lat in lats32 + lats64:
+    for lat in lats32 + lats32p:
         lat.close()
     torch.cuda.empty_cache()
-    return {"grids": len(specs), "lattice_updates": lu,
+    # float64 trajectory sensitivity on the finest mesh (batched float64 is
+    # the same arithmetic as the plain float64 step)
+    kf = max(levels)
+    latsp, stp = build(0, only=kf, perturb=True)
+    timed_batch(latsp, stp)
+    ref = [c for (k, sd), c in zip(specs, lats64) if k == kf]
+    chaos = {"mesh": per_level[kf]["grid"], "steps": stp[0], "rho_max_rel": 0.0, "T_max_rel": 0.0,
+             "perturbation": "initial density moved up by one ulp at every node"}
+    for a, c in zip(latsp, ref):
+        ra, _, _, Ta = a.fields()
+        rc, _, _, Tc = c.fields()
+        chaos["rho_max_rel"] = max(chaos["rho_max_rel"], rel_err(ra, rc))
+        chaos["T_max_rel"] = max(chaos["T_max_rel"], rel_err(Ta, Tc))
+    for lat in latsp + lats64:
+        lat.close()
+    torch.cuda.empty_cache()
+    return {"grids": len(specs), "steps0": steps0, "lattice_updates": lu,
             "fp32_batched": {"wall_s": round(t32, 4), "device_ms": round(ms32, 3),
                              "MLUPS": round(lu / t32 / 1e6, 1), "step_launches": launches,
                              "graph_launches": graphs},
+            "fp32_per_grid": {"wall_s": round(t32p, 4), "MLUPS": round(lu / t32p / 1e6, 1),
+                              "kernel_launches": sum(steps)},
             "fp64_plain_per_grid": {"wall_s": round(t64, 4), "MLUPS": round(lu / t64 / 1e6, 1),
                                     "kernel_launches": sum(steps)},
             "speedup": round(t64 / t32, 3),
+            "speedup_batching_fp32": round(t32p / t32, 3),
+            "speedup_precision_per_grid": round(t64 / t32p, 3),
             "levels": {str(k): v for k, v in per_level.items()},
+            "fp64_trajectory_sensitivity": chaos,
             "accuracy": "max relative rho / T difference, float32 batched vs float64 plain, "
                         "per mesh over its 4 seeds, after the full schedule"}
 
@@ -465,9 +678,9 @@ def droplet_stats(rho, rho_l, rho_v):
 
 def pool_heat_flux(precision, steps, every, tune):
     """Pool boiling 1024 wide x 2048 tall (liquid below 1400, heater 128 wide
-    at 0.95 T_c; mesh 3 of the refinement ladder over a 128 x 256 base with
-    g = -3e-5 there): heat flux entering through the bottom wall
-    (Eq. pool-heat-flux) every `every` steps."""
+    at 0.95 T_c, the rest of the bottom adiabatic; mesh 3 of the refinement
+    ladder over a 128 x 256 base with g = -3e-5 there): the wall heat flux of
+    Eq. pool-heat-flux and the heater's own mean flux every `every` steps."""
     import torch
 
     from paper_2201_04560_amd import Lattice, make_params
@@ -478,60 +691,44 @@ def pool_heat_flux(precision, steps, every, tune):
     lat.init_fields(rho, None, None, T)
     if tune is not None:
         tune.tune(lat, device=device_key())
-    q = []
+    q, qh = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps // every):
         lat.step(every)
-        q.append(lat.norms()["q_bottom"])
+        n = lat.norms()
+        q.append(n["q_bottom"])
+        qh.append(n["q_heater"])
     dt = time.perf_counter() - t0
     r = lat.fields()[0]
     lat.close()
     torch.cuda.empty_cache()
-    # Nusselt number of the heater: the mean wall heat flux over the heater
-    # (Q of Eq. pool-heat-flux times L / L_h) made dimensionless with the
-    # heater length L_h and the liquid conduction scale lambda_l (T_h - T_sat)
+    # Nusselt number of the heater (reading C18): the heater's mean flux made
+    # dimensionless with its length W_h (the held bottom nodes) and the
+    # liquid conduction scale lambda_l (T_h - T_sat); positive into the fluid
     tb = np.broadcast_to(np.asarray(bnd["t_bottom_val"], dtype=np.float64), (nx,))
     t_h, t_sat = float(tb.max()), float(np.min(bnd["t_top_val"]))
-    nu_scale = -nx / (kw["lambda_l"] * (t_h - t_sat))
-    return np.array(q), r, nx * ny * steps / dt / 1e6, dict(kw, nu_scale=nu_scale)
+    w_h = int(n["n_heater"])
+    nu_scale = -w_h / (kw["lambda_l"] * (t_h - t_sat))
+    return np.array(q), np.array(qh), r, nx * ny * steps / dt / 1e6, dict(kw, nu_scale=nu_scale, w_h=w_h)
 
 
-def accuracy_bench(vap_res, case, args, tune):
-    """Float32 shifted storage against the float64 step: droplet radius and
-    coexistence densities after the vaporisation run with rho_ref = rho_v
-    (the timed runs) and rho_ref = mean density; heat flux history of the
-    1024 x 2048 pool."""
-    from paper_2201_04560_amd import LBM_FP32_SHIFTED
-
-    nx, ny, kw, bnd, rho0, T0 = case
-    rl, rv = kw["rho_l"], kw["rho_v"]
-    r64 = vap_res["fp64"]["fields"][0]
-    out = {"vaporisation512": {"after_steps": args.warmup + args.steps,
-                               "fp64": droplet_stats(r64, rl, rv)}}
-    for name, res in (("fp32_rho_ref_rho_v", vap_res["fp32"]),):
-        out["vaporisation512"][name] = droplet_stats(res["fields"][0], rl, rv)
-    kw2 = dict(kw, rho_ref=float(rho0.mean()))
-    r2 = run_lattice((nx, ny, kw2, bnd, rho0, T0), LBM_FP32_SHIFTED, args.warmup, args.steps,
-                     tile_y=vap_res["fp32"]["tile_y"], strip_waves=vap_res["fp32"]["strip_waves"])
-    st = droplet_stats(r2["fields"][0], rl, rv)
-    st["rho_ref"] = kw2["rho_ref"]
-    st["rho_max_rel_vs_fp64"] = rel_err(r2["fields"][0], r64)
-    st["T_max_rel_vs_fp64"] = rel_err(r2["fields"][3], vap_res["fp64"]["fields"][3])
-    out["vaporisation512"]["fp32_rho_ref_mean"] = st
+def accuracy_bench(args, tune):
+    """Float32 shifted storage against the float64 step on the 1024 x 2048
+    pool: wall and heater heat-flux histories and the heater Nusselt number."""
     steps, every = args.pool_steps, max(args.pool_steps // 10, 1)
-    q32, p32, m32, _ = pool_heat_flux(1, steps, every, tune)
-    q64, p64, m64, k64 = pool_heat_flux(0, steps, every, tune)
-    nu32, nu64 = q32 * k64["nu_scale"], q64 * k64["nu_scale"]
-    out["pool1024x2048"] = {
-        "steps": steps, "q_in_every": every,
-        "q_in_fp32": q32.tolist(), "q_in_fp64": q64.tolist(),
-        "q_in_max_rel_diff": float(np.abs(q32 - q64).max() / np.abs(q64).max()),
+    q32, h32, p32, m32, _ = pool_heat_flux(1, steps, every, tune)
+    q64, h64, p64, m64, k64 = pool_heat_flux(0, steps, every, tune)
+    nu32, nu64 = h32 * k64["nu_scale"], h64 * k64["nu_scale"]
+    return {"pool1024x2048": {
+        "steps": steps, "q_every": every, "heater_nodes": k64["w_h"],
+        "q_wall_fp32": q32.tolist(), "q_wall_fp64": q64.tolist(),
+        "q_wall_max_rel_diff": float(np.abs(q32 - q64).max() / np.abs(q64).max()),
+        "q_heater_fp32": h32.tolist(), "q_heater_fp64": h64.tolist(),
         "nusselt_heater_fp32": np.round(nu32, 6).tolist(), "nusselt_heater_fp64": np.round(nu64, 6).tolist(),
         "nusselt_max_rel_diff": float(np.abs(nu32 - nu64).max() / np.abs(nu64).max()),
         "rho_max_rel": rel_err(p32, p64),
-        "MLUPS_fp32_with_norms": round(m32, 1), "MLUPS_fp64_with_norms": round(m64, 1)}
-    return out
+        "MLUPS_fp32_with_norms": round(m32, 1), "MLUPS_fp64_with_norms": round(m64, 1)}}
 
 
 def optional_section(fn, *a, **kw):
@@ -553,16 +750,22 @@ def rel_err(a, b):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--accuracy-steps", type=int, default=20000,
+                    help="length of the float32-vs-float64 comparison on the four seeds (the "
+                         "configuration's 20000 steps)")
     ap.add_argument("--sizing-steps", type=int, default=200)
     ap.add_argument("--no-sizing", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fp32", "fp64", "both"], default="both")
-    ap.add_argument("--profile-case", choices=["vaporisation512", "pool4096", "adjoint256"], default=None,
+    ap.add_argument("--profile-case", choices=["vaporisation512", "vaporisation512x4", "pool4096",
+                                               "adjoint256"], default=None,
                     help="profiling run: only this case (precision from --only), --steps steps, "
                          "plus a device copy of --copy-mib MiB (counter calibration); no JSON. "
-                         "adjoint256: the 256^2 x 500-step heater gradient in both precisions")
+                         "vaporisation512x4: the four seeds in the batched launch timed by the "
+                         "metric; adjoint256: the 256^2 x 500-step heater gradient in both "
+                         "precisions")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--tile-y", type=int, default=0)
     ap.add_argument("--strip-waves", type=int, default=0,
@@ -571,7 +774,7 @@ def main():
                     help="no GPU work: write profiles/traffic.json from the rocprofv3 --pmc "
                          "directories DIR/pmc_<case>_<prec>_<TY>x<W>_<FETCH_SIZE|WRITE_SIZE> "
                          "of --profile-case runs (calibration copy of --copy-mib MiB)")
-    ap.add_argument("--ladder-steps0", type=int, default=50,
+    ap.add_argument("--ladder-steps0", type=int, default=800,
                     help="steps of the coarsest ladder mesh (mesh k runs steps0 * 4^k)")
     ap.add_argument("--no-ladder", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
@@ -623,14 +826,18 @@ def main():
                 f"{r[name]['checkpointed_forward_ms']} ms, plain forward {r[name]['plain_forward_ms']} ms")
         return
     if args.profile_case:
-        pcase = vaporisation_case() if args.profile_case == "vaporisation512" else pool_case()
         for name, prec in (("fp32", LBM_FP32_SHIFTED), ("fp64", LBM_FP64)):
-            if args.only in (name, "both"):
+            if args.only not in (name, "both"):
+                continue
+            if args.profile_case == "vaporisation512x4":
+                ty, w = (args.tile_y, args.strip_waves) if args.tile_y else tune_vap_batch(tune, prec)
+                r = run_vap_batch(prec, args.warmup, args.steps, ty, w, want_fields=False)
+            else:
+                pcase = vaporisation_case() if args.profile_case == "vaporisation512" else pool_case()
                 r = run_lattice(pcase, prec, args.warmup, args.steps, want_fields=False,
                                 tile_y=args.tile_y, tune=tune, strip_waves=args.strip_waves)
-                log(f"profile: {args.profile_case} {name} kernel {r['kernel_ms_avg'] * 1e3:.2f} us "
-                    f"avg over {r['launches']} launches, tile_y {r['tile_y']}, "
-                    f"waves {r['strip_waves']}")
+            log(f"profile: {args.profile_case} {name} kernel {r['kernel_ms_avg'] * 1e3:.2f} us "
+                f"avg over {r['launches']} launches, tile_y {r['tile_y']}, waves {r['strip_waves']}")
         if args.copy_mib > 0:
             n = args.copy_mib * (1 << 20) // 4
             src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -643,14 +850,23 @@ def main():
 
     case = vaporisation_case()
     nx, ny = case[0], case[1]
-    nodes = nx * ny
+    nodes = len(SEEDS) * nx * ny
     res = {}
+    tiles = {}
     for name, prec in (("fp32", LBM_FP32_SHIFTED), ("fp64", LBM_FP64)):
         if args.only not in (name, "both"):
             continue
-        log(f"bench: {name} {nx}x{ny} vaporisation, warmup {args.warmup}, steps {args.steps}")
-        res[name] = run_lattice(case, prec, args.warmup, args.steps, tile_y=args.tile_y, tune=tune,
-                                strip_waves=args.strip_waves)
+        if name == "fp32":
+            ty, w = (args.tile_y, args.strip_waves) if args.tile_y else tune_vap_batch(tune, prec)
+            tiles[name] = (ty, w)
+            log(f"bench: fp32 4 x {nx}x{ny} vaporisation batch, tile_y {ty}, waves {w}, warmup "
+                f"{args.warmup}, steps {args.steps}")
+            res[name] = run_vap_batch(prec, args.warmup, args.steps, ty, w)
+        else:
+            log(f"bench: fp64 plain step, 4 x {nx}x{ny} one lattice after another, warmup "
+                f"{args.warmup}, steps {args.steps}")
+            res[name] = run_vap_plain(prec, args.warmup, args.steps, tile_y=args.tile_y,
+                                      waves=args.strip_waves)
         r = res[name]
         log(f"bench: {name} {args.steps * nodes / r['wall_s'] / 1e6:.0f} MLUPS, kernel "
             f"{r['kernel_ms_avg'] * 1e3:.2f} us avg over {r['launches']} launches, "
@@ -659,6 +875,8 @@ def main():
     main_name = "fp32" if "fp32" in res else "fp64"
     m = res[main_name]
     value = args.steps * nodes / m["wall_s"] / 1e6
+    per_launch_nodes = nodes if main_name == "fp32" else nx * ny
+    traffic_key = "vaporisation512x4_fp32" if main_name == "fp32" else "vaporisation512_fp64"
     out = {
         "metric": "MLUPS + % HBM roofline, FP32 fused vs FP64 plain step, at stated rho/T error",
         "value": round(value, 1),
@@ -672,43 +890,59 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if main_name == "fp32" else "f64",
         "data": "synthetic",
-        "config": {"workload": "droplet vaporisation 512x512, PR a=2/49 b=2/21, r=60 at 0.86 Tc "
-                               "in vapour held at 0.95 Tc, sigma=kappa=0.1, cv=6, lambda=2/3, no "
-                               "gravity, seed 0 (+-0.5 interface jitter)",
-                   "nx": nx, "ny": ny, "storage": "f32 shifted populations (f - w rho_v) + f32 T; "
-                   "f64 EOS/psi/forces and reductions", "steps_total": args.warmup + args.steps,
+        "config": {"workload": "droplet vaporisation 512x512, seeds 0-3 (+-0.5 interface jitter), "
+                               "PR a=2/49 b=2/21, r=60 at 0.86 Tc in vapour held at 0.95 Tc, "
+                               "sigma=kappa=0.1, cv=6, lambda=2/3, no gravity; a step advances the "
+                               "four seeds by one time step",
+                   "nx": nx, "ny": ny, "lattices": len(SEEDS),
+                   "storage": "f32 shifted populations (f - w rho_v) + f32 T; f64 EOS/psi/forces "
+                              "and reductions" if main_name == "fp32" else "f64",
+                   "launch": "one batched multi-lattice launch per step, graph-replayed"
+                             if main_name == "fp32" else "one launch per lattice and step",
+                   "steps_total": args.warmup + args.steps,
                    "tile_y": m["tile_y"], "strip_waves": m["strip_waves"]},
-        "roofline": roofline(main_name == "fp32", nodes, m["kernel_ms_avg"],
-                             measured_traffic(f"vaporisation512_{main_name}", m["tile_y"],
-                                              m["strip_waves"])),
+        "roofline": roofline(main_name == "fp32", per_launch_nodes, m["kernel_ms_avg"],
+                             measured_traffic(traffic_key, m["tile_y"], m["strip_waves"])),
     }
     copy_gbs = copy_bandwidth()
     log(f"bench: device copy {copy_gbs} GB/s")
     with_copy_fraction(out["roofline"], copy_gbs)
+    if main_name == "fp32":
+        out["batch_bitwise_vs_solo"] = batch_bitwise_vs_solo(m, LBM_FP32_SHIFTED,
+                                                             args.warmup + args.steps)
     if "fp32" in res and "fp64" in res:
         f32, f64 = res["fp32"], res["fp64"]
-        r32, _, _, T32 = f32["fields"]
-        r64, _, _, T64 = f64["fields"]
         out["fp64_plain"] = {
             "value": round(args.steps * nodes / f64["wall_s"] / 1e6, 1), "unit": "MLUPS",
             "tile_y": f64["tile_y"], "strip_waves": f64["strip_waves"],
             "ms_per_step": round(f64["wall_s"] * 1e3 / args.steps, 5),
+            "launch": "one launch per lattice and step, the four lattices one after another",
             "roofline": with_copy_fraction(
-                roofline(False, nodes, f64["kernel_ms_avg"],
+                roofline(False, nx * ny, f64["kernel_ms_avg"],
                          measured_traffic("vaporisation512_fp64", f64["tile_y"], f64["strip_waves"])),
                 copy_gbs),
         }
         out["speedup_fp32_vs_fp64"] = round(f64["wall_s"] / f32["wall_s"], 3)
-        out["fp32_error_vs_fp64"] = {
-            "after_steps": args.warmup + args.steps,
-            "rho_max_rel": rel_err(r32, r64), "T_max_rel": rel_err(T32, T64),
-            "mass_rel": abs(f32["norms"]["mass"] / f64["norms"]["mass"] - 1),
-            "liquid_fraction_fp32": float((r32 > 0.5 * (case[2]["rho_l"] + case[2]["rho_v"])).mean()),
-            "liquid_fraction_fp64": float((r64 > 0.5 * (case[2]["rho_l"] + case[2]["rho_v"])).mean()),
-        }
+        if not args.no_accuracy:
+            log(f"bench: float32 vs float64 accuracy, 4 seeds x {args.accuracy_steps} steps")
+            out["fp32_error_vs_fp64"] = optional_section(accuracy_20k, args.accuracy_steps, tune)
+    # the single lattice (seed 0) as in the plain per-lattice runs, for reference
+    single = {}
+    for name, prec in (("fp32", LBM_FP32_SHIFTED), ("fp64", LBM_FP64)):
+        if args.only not in (name, "both"):
+            continue
+        r = run_lattice(case, prec, args.warmup, args.steps, want_fields=False, tile_y=args.tile_y,
+                        tune=tune, strip_waves=args.strip_waves)
+        single[name] = {"value": round(args.steps * nx * ny / r["wall_s"] / 1e6, 1), "unit": "MLUPS",
+                        "tile_y": r["tile_y"], "strip_waves": r["strip_waves"],
+                        "roofline": with_copy_fraction(
+                            roofline(name == "fp32", nx * ny, r["kernel_ms_avg"],
+                                     measured_traffic(f"vaporisation512_{name}", r["tile_y"],
+                                                      r["strip_waves"])), copy_gbs)}
+    out["single_lattice_seed0"] = single
     if "fp32" in res and "fp64" in res and not args.no_accuracy:
-        log("bench: float32 accuracy (rho_ref variants, pool heat flux)")
-        out["fp32_accuracy"] = optional_section(accuracy_bench, res, case, args, tune)
+        log("bench: pool heat flux and heater Nusselt number, float32 vs float64")
+        out["fp32_accuracy"] = optional_section(accuracy_bench, args, tune)
     if not args.no_sizing:
         pc = pool_case()
         sz = {}

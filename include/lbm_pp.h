@@ -248,6 +248,13 @@ const char* lbm_batch_last_error(const lbm_batch* b);
  * into a hipGraph once and replayed.  The result equals lbm_step() on each
  * context (same kernels, same arithmetic).  Asynchronous. */
 lbm_status lbm_batch_run(lbm_batch* b, const int64_t* steps, int32_t use_graph);
+/* Plan the schedule lbm_batch_run(b, steps, use_graph) would run from the
+ * lattices' current states, upload its argument tables and capture (and
+ * instantiate) its graphs, without launching anything or advancing a
+ * lattice: the run that follows replays them at once.  A batch keeps its
+ * instantiated graphs until lbm_batch_destroy() and re-uploads only tables
+ * whose content changed, so repeated runs of one schedule need neither. */
+lbm_status lbm_batch_prepare(lbm_batch* b, const int64_t* steps, int32_t use_graph);
 /* Device time of the last run (HIP events), number of step launches it
  * covered and of graph launches used.  Waits for the run. */
 lbm_status lbm_batch_last_time(lbm_batch* b, double* ms, int64_t* kernel_launches,

@@ -79,6 +79,7 @@ SIGNATURES = [
     ("lbm_batch_destroy", None, [c_void_p]),
     ("lbm_batch_last_error", ctypes.c_char_p, [c_void_p]),
     ("lbm_batch_run", c_int32, [c_void_p, P(c_int64), c_int32]),
+    ("lbm_batch_prepare", c_int32, [c_void_p, P(c_int64), c_int32]),
     ("lbm_batch_last_time", c_int32, [c_void_p, _DP, P(c_int64), P(c_int64)]),
     ("lbm_autotune_tile_y", c_int32, [c_void_p, P(c_int32), c_int32, c_int32, P(c_int32), _DP]),
     ("lbm_tile_candidates", c_int32, [c_void_p, c_int32, P(c_int32), c_int32, P(c_int32)]),

@@ -33,6 +33,7 @@ size_t al(size_t v) { return (v + 255) / 256 * 256; }
 struct LaunchRec {
   int table = -1;       // step descriptor table (update_T group 0/1 merged by signature)
   int thermal = 0;      // energy update in this launch
+  int waves = 1;        // waves per strip (2: the two-wave march, energy launches only)
   int ngrid = 0;
   int nblocks = 0;
   int wall_table = -1;  // -1: no wall-closure launch
@@ -52,6 +53,13 @@ struct lbm_batch {
   std::string err;
   bool timed = false;
   int64_t launches = 0, graph_launches = 0;
+  // argument tables as they are in device memory (index -> bytes, starts
+  // included): a run re-uploads only the tables whose content changed
+  std::vector<std::string> dtab, dwtab;
+  // instantiated graphs of repeated launch pairs, keyed by the pair's launch
+  // shape and length; they address the tables by index, so they stay valid
+  // across runs and are replayed without another capture
+  std::map<std::string, hipGraphExec_t> graphs;
 
   char* step_tab(int t) const { return dev + size_t(t) * al(kMaxGrids * sdesc); }
   char* wall_tab(int t) const {
@@ -129,6 +137,8 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int32_t n, void* dev_buf, size
 
 void lbm_batch_destroy(lbm_batch* b) {
   if (!b) return;
+  for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+  b->graphs.clear();
   if (b->own) (void)hipStreamDestroy(b->own);
   if (b->join) (void)hipEventDestroy(b->join);
   if (b->t0) (void)hipEventDestroy(b->t0);
@@ -142,13 +152,28 @@ static lbm_status issue(lbm_batch* b, const LaunchRec& r, hipStream_t st) {
   if (r.wall_table >= 0)
     BTRY(b, launch_wall_multi(b->fp32, b->wall_tab(r.wall_table), b->wstarts(r.wall_table), r.ngrid,
                               r.wall_nblocks, st));
-  BTRY(b, launch_step_multi(b->fp32, b->wall_mode, r.thermal, b->step_tab(r.table), b->starts(r.table), r.ngrid,
-                            r.nblocks, st));
+  BTRY(b, launch_step_multi(b->fp32, b->wall_mode, r.thermal, r.waves, b->step_tab(r.table),
+                            b->starts(r.table), r.ngrid, r.nblocks, st));
   return LBM_OK;
 }
 
-lbm_status lbm_batch_run(lbm_batch* b, const int64_t* steps, int32_t use_graph) {
-  if (!b || !steps) return LBM_E_INVAL;
+// number of lattices of a table signature: ngrid descriptors of `desc`
+// bytes followed by ngrid + 1 workgroup starts
+static size_t recs_ngrid_of(const std::string& sig, size_t desc) {
+  return (sig.size() - sizeof(int)) / (desc + sizeof(int));
+}
+
+struct SimState {
+  int cur, Tcur, pcur, npart;
+  int64_t step;
+};
+
+// Simulate the host state machine of every lattice over the schedule, build
+// the launch records and bring the argument tables in device memory up to
+// date (only changed tables are copied).  end[] receives each lattice's state
+// after the schedule.
+static lbm_status plan_run(lbm_batch* b, const int64_t* steps, std::vector<LaunchRec>& recs,
+                           std::vector<SimState>& st) {
   const int n = int(b->g.size());
   int64_t T = 0;
   for (int i = 0; i < n; ++i) {
@@ -156,17 +181,11 @@ lbm_status lbm_batch_run(lbm_batch* b, const int64_t* steps, int32_t use_graph) 
     if (!b->g[i]->initialized) return fail(b->g[i], LBM_E_STATE, "batch member not initialised");
     T = std::max(T, steps[i]);
   }
-  // --- simulate the host state machine of every lattice, build launch records
-  struct St {
-    int cur, Tcur, pcur, npart;
-    int64_t step;
-  };
-  std::vector<St> st(n);
+  st.resize(n);
   for (int i = 0; i < n; ++i) st[i] = {b->g[i]->cur, b->g[i]->Tcur, b->g[i]->pcur, b->g[i]->npart, b->g[i]->step};
   std::map<std::string, int> seen, wseen;
   std::vector<std::string> tabs, wtabs;
-  std::vector<std::vector<int>> tstarts, wtstarts;
-  std::vector<LaunchRec> recs;
+  recs.clear();
   recs.reserve(size_t(T) * 2);
   std::vector<char> buf(b->sdesc), wbuf(b->wdesc);
   std::vector<int> ut_t(n);
@@ -174,8 +193,10 @@ lbm_status lbm_batch_run(lbm_batch* b, const int64_t* steps, int32_t use_graph) 
     // lattices active in this launch (-1: done), and whether T is updated
     for (int i = 0; i < n; ++i)
       ut_t[i] = t >= steps[i] ? -1 : int(b->g[i]->p.thermal && st[i].step >= b->g[i]->p.n_iso);
-    // one record per group of equal energy-update flag
-    for (int thermal = 0; thermal < 2; ++thermal) {
+    // one record per group of equal energy-update flag and waves per strip
+    // (no update; update with one wave; update with two waves)
+    for (int grp = 0; grp < 3; ++grp) {
+      const int thermal = grp > 0, waves = grp == 2 ? 2 : 1;
       std::string sig, wsig;
       std::vector<int> starts(1, 0), wstarts(1, 0);
       int ng = 0;
@@ -184,6 +205,7 @@ lbm_status lbm_batch_run(lbm_batch* b, const int64_t* steps, int32_t use_graph) 
         lbm_ctx* c = b->g[i];
         const int ut = ut_t[i];
         if (ut != thermal) continue;
+        if (ut && (lbm_get_strip_waves(c) == 2 ? 2 : 1) != waves) continue;
         // arguments of this lattice in its simulated state
         const int sc = c->cur, sT = c->Tcur, sp = c->pcur, sn = c->npart;
         c->cur = st[i].cur;
@@ -227,6 +249,7 @@ lbm_status lbm_batch_run(lbm_batch* b, const int64_t* steps, int32_t use_graph) 
       sig.append(reinterpret_cast<const char*>(starts.data()), starts.size() * sizeof(int));
       LaunchRec r;
       r.thermal = thermal;
+      r.waves = waves;
       r.ngrid = ng;
       r.nblocks = starts.back();
       auto it = seen.find(sig);
@@ -237,7 +260,6 @@ lbm_status lbm_batch_run(lbm_batch* b, const int64_t* steps, int32_t use_graph) 
         }
         it = seen.emplace(sig, int(tabs.size())).first;
         tabs.push_back(sig);
-        tstarts.push_back(starts);
       }
       r.table = it->second;
       if (any_wall) {
@@ -250,7 +272,6 @@ lbm_status lbm_batch_run(lbm_batch* b, const int64_t* steps, int32_t use_graph) 
           }
           wi = wseen.emplace(wsig, int(wtabs.size())).first;
           wtabs.push_back(wsig);
-          wtstarts.push_back(wstarts);
         }
         r.wall_table = wi->second;
         r.wall_nblocks = wstarts.back();
@@ -258,69 +279,136 @@ lbm_status lbm_batch_run(lbm_batch* b, const int64_t* steps, int32_t use_graph) 
       recs.push_back(r);
     }
   }
-  // --- upload the argument tables (host -> device, once)
+  // --- bring the device tables up to date (host -> device, changed ones only)
+  bool copied = false;
   for (size_t k = 0; k < tabs.size(); ++k) {
+    if (k < b->dtab.size() && b->dtab[k] == tabs[k]) continue;
     const std::string& s = tabs[k];
-    const size_t db = s.size() - tstarts[k].size() * sizeof(int);
+    const size_t nstart = size_t(recs_ngrid_of(s, b->sdesc)) + 1;
+    const size_t db = s.size() - nstart * sizeof(int);
     BTRY(b, hipMemcpyAsync(b->step_tab(int(k)), s.data(), db, hipMemcpyHostToDevice, b->own));
-    BTRY(b, hipMemcpyAsync(b->starts(int(k)), tstarts[k].data(), tstarts[k].size() * sizeof(int),
-                           hipMemcpyHostToDevice, b->own));
+    BTRY(b, hipMemcpyAsync(b->starts(int(k)), s.data() + db, nstart * sizeof(int), hipMemcpyHostToDevice,
+                           b->own));
+    if (b->dtab.size() <= k) b->dtab.resize(k + 1);
+    b->dtab[k] = s;
+    copied = true;
   }
   for (size_t k = 0; k < wtabs.size(); ++k) {
-    const size_t db = wtabs[k].size() - wtstarts[k].size() * sizeof(int);
-    BTRY(b, hipMemcpyAsync(b->wall_tab(int(k)), wtabs[k].data(), db, hipMemcpyHostToDevice, b->own));
-    BTRY(b, hipMemcpyAsync(b->wstarts(int(k)), wtstarts[k].data(), wtstarts[k].size() * sizeof(int),
-                           hipMemcpyHostToDevice, b->own));
+    if (k < b->dwtab.size() && b->dwtab[k] == wtabs[k]) continue;
+    const std::string& s = wtabs[k];
+    const size_t nstart = size_t(recs_ngrid_of(s, b->wdesc)) + 1;
+    const size_t db = s.size() - nstart * sizeof(int);
+    BTRY(b, hipMemcpyAsync(b->wall_tab(int(k)), s.data(), db, hipMemcpyHostToDevice, b->own));
+    BTRY(b, hipMemcpyAsync(b->wstarts(int(k)), s.data() + db, nstart * sizeof(int), hipMemcpyHostToDevice,
+                           b->own));
+    if (b->dwtab.size() <= k) b->dwtab.resize(k + 1);
+    b->dwtab[k] = s;
+    copied = true;
   }
-  BTRY(b, hipStreamSynchronize(b->own));
-  // order after the caller's earlier work
-  BTRY(b, hipEventRecord(b->join, b->user));
-  BTRY(b, hipStreamWaitEvent(b->own, b->join, 0));
-  BTRY(b, hipEventRecord(b->t0, b->own));
-  // --- issue: runs of a repeated pair of records go through a captured graph
+  if (copied) BTRY(b, hipStreamSynchronize(b->own));
+  return LBM_OK;
+}
+
+static bool same_rec(const LaunchRec& x, const LaunchRec& y) {
+  return x.table == y.table && x.wall_table == y.wall_table && x.thermal == y.thermal &&
+         x.waves == y.waves && x.ngrid == y.ngrid && x.nblocks == y.nblocks &&
+         x.wall_nblocks == y.wall_nblocks;
+}
+
+// The graph of m repetitions of the launch pair (x, y), captured on the
+// batch's stream on first use and kept until the batch is destroyed.
+static lbm_status pair_graph(lbm_batch* b, const LaunchRec& x, const LaunchRec& y, size_t m,
+                             hipGraphExec_t* out) {
+  const int key_i[] = {x.table, x.wall_table, x.thermal, x.waves, x.ngrid, x.nblocks, x.wall_nblocks,
+                       y.table, y.wall_table, y.thermal, y.waves, y.ngrid, y.nblocks, y.wall_nblocks,
+                       int(m)};
+  const std::string key(reinterpret_cast<const char*>(key_i), sizeof key_i);
+  auto it = b->graphs.find(key);
+  if (it != b->graphs.end()) {
+    *out = it->second;
+    return LBM_OK;
+  }
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  BTRY(b, hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal));
+  for (size_t k = 0; k < m; ++k) {
+    lbm_status s1 = issue(b, x, b->own);
+    lbm_status s2 = s1 == LBM_OK ? issue(b, y, b->own) : s1;
+    if (s2 != LBM_OK) {
+      (void)hipStreamEndCapture(b->own, &graph);
+      return s2;
+    }
+  }
+  BTRY(b, hipStreamEndCapture(b->own, &graph));
+  const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  BTRY(b, e);
+  b->graphs.emplace(key, exec);
+  *out = exec;
+  return LBM_OK;
+}
+
+// Walk the records: runs of a repeated pair go through cached graphs of up
+// to kGraphPairs pairs, the rest are launched one by one.  launch = false
+// only makes sure the graphs exist (lbm_batch_prepare).
+static lbm_status issue_all(lbm_batch* b, const std::vector<LaunchRec>& recs, int use_graph, bool launch) {
   size_t i = 0;
-  b->launches = 0;
-  b->graph_launches = 0;
-  auto same = [](const LaunchRec& x, const LaunchRec& y) {
-    return x.table == y.table && x.wall_table == y.wall_table && x.thermal == y.thermal;
-  };
   while (i < recs.size()) {
     size_t reps = 0;
     if (use_graph && i + 3 < recs.size()) {
-      while (i + 2 * reps + 3 < recs.size() && same(recs[i + 2 * reps + 2], recs[i]) &&
-             same(recs[i + 2 * reps + 3], recs[i + 1]))
+      while (i + 2 * reps + 3 < recs.size() && same_rec(recs[i + 2 * reps + 2], recs[i]) &&
+             same_rec(recs[i + 2 * reps + 3], recs[i + 1]))
         ++reps;
       ++reps;  // the first pair itself
     }
     if (reps >= 2) {
       const size_t m = std::min<size_t>(reps, kGraphPairs);
-      hipGraph_t graph;
       hipGraphExec_t exec;
-      BTRY(b, hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal));
-      for (size_t k = 0; k < m; ++k) {
-        lbm_status s1 = issue(b, recs[i], b->own);
-        lbm_status s2 = s1 == LBM_OK ? issue(b, recs[i + 1], b->own) : s1;
-        if (s2 != LBM_OK) {
-          (void)hipStreamEndCapture(b->own, &graph);
-          return s2;
-        }
-      }
-      BTRY(b, hipStreamEndCapture(b->own, &graph));
-      BTRY(b, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+      lbm_status s = pair_graph(b, recs[i], recs[i + 1], m, &exec);
+      if (s != LBM_OK) return s;
       const size_t rounds = reps / m;
-      for (size_t k = 0; k < rounds; ++k) BTRY(b, hipGraphLaunch(exec, b->own));
-      b->graph_launches += int64_t(rounds);
-      BTRY(b, hipGraphExecDestroy(exec));
-      BTRY(b, hipGraphDestroy(graph));
-      b->launches += int64_t(rounds * m * 2);
+      if (launch) {
+        for (size_t k = 0; k < rounds; ++k) BTRY(b, hipGraphLaunch(exec, b->own));
+        b->graph_launches += int64_t(rounds);
+        b->launches += int64_t(rounds * m * 2);
+      }
       i += rounds * m * 2;
       continue;
     }
-    lbm_status s = issue(b, recs[i], b->own);
-    if (s != LBM_OK) return s;
-    ++b->launches;
+    if (launch) {
+      lbm_status s = issue(b, recs[i], b->own);
+      if (s != LBM_OK) return s;
+      ++b->launches;
+    }
     ++i;
   }
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_prepare(lbm_batch* b, const int64_t* steps, int32_t use_graph) {
+  if (!b || !steps) return LBM_E_INVAL;
+  std::vector<LaunchRec> recs;
+  std::vector<SimState> st;
+  lbm_status s = plan_run(b, steps, recs, st);
+  if (s != LBM_OK) return s;
+  return issue_all(b, recs, use_graph, false);
+}
+
+lbm_status lbm_batch_run(lbm_batch* b, const int64_t* steps, int32_t use_graph) {
+  if (!b || !steps) return LBM_E_INVAL;
+  const int n = int(b->g.size());
+  std::vector<LaunchRec> recs;
+  std::vector<SimState> st;
+  lbm_status s = plan_run(b, steps, recs, st);
+  if (s != LBM_OK) return s;
+  // order after the caller's earlier work
+  BTRY(b, hipEventRecord(b->join, b->user));
+  BTRY(b, hipStreamWaitEvent(b->own, b->join, 0));
+  BTRY(b, hipEventRecord(b->t0, b->own));
+  b->launches = 0;
+  b->graph_launches = 0;
+  s = issue_all(b, recs, use_graph, true);
+  if (s != LBM_OK) return s;
   BTRY(b, hipEventRecord(b->t1, b->own));
   // the caller's stream continues after the batch
   BTRY(b, hipEventRecord(b->join, b->own));

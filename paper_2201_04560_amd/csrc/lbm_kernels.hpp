@@ -124,8 +124,10 @@ size_t step_desc_bytes(int fp32);
 void fill_step_desc(const LaunchStep& L, void* out);
 // wall_mode: 0 periodic, 1 psi-based walls, 2 some lattice has modified-psi
 // walls or an outflow top
-hipError_t launch_step_multi(int fp32, int wall_mode, int thermal, const void* desc, const int* start,
-                             int ngrid, int nblocks, hipStream_t st);
+// waves = 2 (energy-update launches only): two waves per strip; every
+// lattice of the launch must satisfy two_wave_fits()
+hipError_t launch_step_multi(int fp32, int wall_mode, int thermal, int waves, const void* desc,
+                             const int* start, int ngrid, int nblocks, hipStream_t st);
 size_t wall_desc_bytes(int fp32);
 void fill_wall_desc(const LaunchWall& L, void* out);
 hipError_t launch_wall_multi(int fp32, const void* desc, const int* start, int ngrid, int nblocks,

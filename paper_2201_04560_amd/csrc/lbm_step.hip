@@ -1134,6 +1134,18 @@ void lbm_march_multi_kernel(const StepArgs<S, C>* __restrict__ desc, const int* 
   march_body<S, C, WM, THERMAL, MODE_STEP, 1, false>(desc[g], O, b - start[g]);
 }
 
+// the batched launch with two waves per strip (energy step; see march_body)
+template <class S, class C, int WM>
+__global__ __launch_bounds__(2 * kLanes) __attribute__((amdgpu_waves_per_eu(WavesPerEU<S>::value, 8)))
+void lbm_march2_multi_kernel(const StepArgs<S, C>* __restrict__ desc, const int* __restrict__ start,
+                             int ngrid) {
+  const int b = blockIdx.x;
+  int g = 0;
+  while (g + 1 < ngrid && b >= start[g + 1]) ++g;
+  const MacroOut O{};
+  march_body<S, C, WM, true, MODE_STEP, 1, true>(desc[g], O, b - start[g]);
+}
+
 // ------------------------------------------------------------- launchers
 template <class C>
 static PhysC<C> phys_c(const Phys& p) {
@@ -1254,30 +1266,35 @@ void fill_step_desc(const LaunchStep& L, void* out) {
 }
 
 template <class S, class C, int WM, bool THERMAL>
-static void launch_multi_t(const void* desc, const int* start, int ngrid, int nblocks, hipStream_t st) {
-  hipLaunchKernelGGL((lbm_march_multi_kernel<S, C, WM, THERMAL>), dim3(nblocks), dim3(kLanes), 0, st,
-                     static_cast<const StepArgs<S, C>*>(desc), start, ngrid);
+static void launch_multi_t(const void* desc, const int* start, int ngrid, int nblocks, int waves,
+                           hipStream_t st) {
+  if (THERMAL && waves == 2)
+    hipLaunchKernelGGL((lbm_march2_multi_kernel<S, C, WM>), dim3(nblocks), dim3(2 * kLanes), 0, st,
+                       static_cast<const StepArgs<S, C>*>(desc), start, ngrid);
+  else
+    hipLaunchKernelGGL((lbm_march_multi_kernel<S, C, WM, THERMAL>), dim3(nblocks), dim3(kLanes), 0, st,
+                       static_cast<const StepArgs<S, C>*>(desc), start, ngrid);
 }
 
 template <class S, class C>
 static void launch_multi_s(int wm, int thermal, const void* desc, const int* start, int ngrid,
-                           int nblocks, hipStream_t st) {
+                           int nblocks, int waves, hipStream_t st) {
   if (wm == 2) {
-    if (thermal) launch_multi_t<S, C, 2, true>(desc, start, ngrid, nblocks, st);
-    else launch_multi_t<S, C, 2, false>(desc, start, ngrid, nblocks, st);
+    if (thermal) launch_multi_t<S, C, 2, true>(desc, start, ngrid, nblocks, waves, st);
+    else launch_multi_t<S, C, 2, false>(desc, start, ngrid, nblocks, waves, st);
   } else if (wm == 1) {
-    if (thermal) launch_multi_t<S, C, 1, true>(desc, start, ngrid, nblocks, st);
-    else launch_multi_t<S, C, 1, false>(desc, start, ngrid, nblocks, st);
+    if (thermal) launch_multi_t<S, C, 1, true>(desc, start, ngrid, nblocks, waves, st);
+    else launch_multi_t<S, C, 1, false>(desc, start, ngrid, nblocks, waves, st);
   } else {
-    if (thermal) launch_multi_t<S, C, 0, true>(desc, start, ngrid, nblocks, st);
-    else launch_multi_t<S, C, 0, false>(desc, start, ngrid, nblocks, st);
+    if (thermal) launch_multi_t<S, C, 0, true>(desc, start, ngrid, nblocks, waves, st);
+    else launch_multi_t<S, C, 0, false>(desc, start, ngrid, nblocks, waves, st);
   }
 }
 
-hipError_t launch_step_multi(int fp32, int wall_mode, int thermal, const void* desc, const int* start,
-                             int ngrid, int nblocks, hipStream_t st) {
-  if (fp32) launch_multi_s<float, float>(wall_mode, thermal, desc, start, ngrid, nblocks, st);
-  else launch_multi_s<double, double>(wall_mode, thermal, desc, start, ngrid, nblocks, st);
+hipError_t launch_step_multi(int fp32, int wall_mode, int thermal, int waves, const void* desc,
+                             const int* start, int ngrid, int nblocks, hipStream_t st) {
+  if (fp32) launch_multi_s<float, float>(wall_mode, thermal, desc, start, ngrid, nblocks, waves, st);
+  else launch_multi_s<double, double>(wall_mode, thermal, desc, start, ngrid, nblocks, waves, st);
   return hipGetLastError();
 }
 

@@ -106,48 +106,57 @@ class TileCache:
 
     def tune_batch(self, make_lattices, device="",
                    candidates=(4, 6, 8, 12, 13, 16, 20, 24, 26, 32, 40, 48, 52, 64, 80, 96, 128),
-                   steps=10):
-        """Strip height for same-shaped lattices advanced together by one
-        batched launch (one wave per strip).  A batch holds n times the
+                   steps=10, waves=(1,), with_waves=False):
+        """Strip height (and waves per strip) for same-shaped lattices
+        advanced together by one batched launch.  A batch holds n times the
         workgroups of one lattice, so it can afford taller strips (fewer
         recomputed halo rows) than the lattice alone.  On a miss, times the
-        batched launch for each candidate on throwaway lattices from
-        make_lattices() (initialised, same shape) and caches the fastest
-        under the lattice key + "/batch<n>".  Returns the height."""
+        batched launch for each candidate height and each entry of `waves`
+        (2: the two-wave march, energy-equation lattices) on throwaway
+        lattices from make_lattices() (initialised, same shape) and caches the
+        fastest under the lattice key + "/batch<n>" (+ "w12" when two waves
+        were tried).  Returns the height, or (height, waves) with
+        with_waves=True."""
         lats = None
         key = None
         e = None
         try:
             lats = make_lattices()
             n = len(lats)
-            key = self.key(lats[0].p, f"{device}/batch{n}")
+            ws = tuple(w for w in waves if w == 1 or lats[0].p.thermal)
+            tag = "" if ws == (1,) else "w" + "".join(str(w) for w in ws)
+            key = self.key(lats[0].p, f"{device}/batch{n}{tag}")
             e = self.table.get(key)
             if e is None:
                 from .sim import Batch
 
                 best, tried = None, []
-                for ty in candidates:
-                    if ty > max(lats[0].ny, 2):
-                        continue
-                    for lat in lats:
-                        lat.tile_y = ty
-                        lat.strip_waves = 1
-                    b = Batch(lats)
-                    try:
-                        b.run([2] * n)
-                        b.run([steps] * n)
-                        ms = b.last_time()[0] / steps
-                    finally:
-                        b.close()
-                    tried.append(ty)
-                    if best is None or ms < best[1]:
-                        best = (ty, ms)
-                e = {"tile_y": best[0], "strip_waves": 1, "ms_per_step": best[1], "candidates": tried}
+                for w in ws:
+                    for ty in candidates:
+                        if ty > max(lats[0].ny, 2):
+                            continue
+                        for lat in lats:
+                            lat.tile_y = ty
+                            lat.strip_waves = w
+                        b = Batch(lats)
+                        try:
+                            b.run([2] * n)
+                            b.run([steps] * n)
+                            ms = b.last_time()[0] / steps
+                        finally:
+                            b.close()
+                        tried.append([ty, w])
+                        if best is None or ms < best[2]:
+                            best = (ty, w, ms)
+                e = {"tile_y": best[0], "strip_waves": best[1], "ms_per_step": best[2],
+                     "candidates": tried}
                 self.table[key] = e
                 self._save()
         finally:
             for lat in lats or []:
                 lat.close()
+        if with_waves:
+            return int(e["tile_y"]), int(e.get("strip_waves", 1))
         return int(e["tile_y"])
 
     def _save(self):

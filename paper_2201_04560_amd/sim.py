@@ -251,6 +251,14 @@ class Batch:
         arr = (ctypes.c_int64 * len(steps))(*[int(s) for s in steps])
         self._check(lib().lbm_batch_run(self._b, arr, 1 if use_graph else 0), "lbm_batch_run")
 
+    def prepare(self, steps, use_graph=True):
+        """Upload the tables and capture the graphs of run(steps) without
+        running it (the following run replays them at once)."""
+        if len(steps) != len(self.lattices):
+            raise ValueError("one step count per lattice")
+        arr = (ctypes.c_int64 * len(steps))(*[int(s) for s in steps])
+        self._check(lib().lbm_batch_prepare(self._b, arr, 1 if use_graph else 0), "lbm_batch_prepare")
+
     def last_time(self):
         """(device ms, step launches, graph launches) of the last run."""
         ms, nl, ng = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()

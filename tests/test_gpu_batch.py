@@ -40,26 +40,31 @@ def _drop_case(n, seed):
     return c, rho, T
 
 
-def _make(case, precision=0, tile_y=0):
+def _make(case, precision=0, tile_y=0, waves=0):
     from paper_2201_04560_amd import Lattice
 
     c, rho, T = case
-    lat = Lattice(cases.lib_params(c, precision=precision, tile_y=tile_y))
+    lat = Lattice(cases.lib_params(c, precision=precision, tile_y=tile_y, strip_waves=waves))
     cases.lib_boundary(lat, c)
     lat.init_fields(rho, None, None, T)
     return lat
 
 
-def _run_pair(case_list, steps, precision, use_graph, tiles=None, runs=1):
+def _run_pair(case_list, steps, precision, use_graph, tiles=None, runs=1, waves=0, prepare=False):
     from paper_2201_04560_amd import Batch
 
     tiles = tiles or [0] * len(case_list)
-    solo = [_make(cs, precision, ty) for cs, ty in zip(case_list, tiles)]
-    grouped = [_make(cs, precision, ty) for cs, ty in zip(case_list, tiles)]
+    solo = [_make(cs, precision, ty, waves) for cs, ty in zip(case_list, tiles)]
+    grouped = [_make(cs, precision, ty, waves) for cs, ty in zip(case_list, tiles)]
     b = Batch(grouped)
     for _ in range(runs):
         for lat, n in zip(solo, steps):
             lat.step(n)
+        if prepare:
+            before = [bl.populations() for bl in grouped]
+            b.prepare(steps, use_graph=use_graph)
+            for bl, f0 in zip(grouped, before):  # prepare launches nothing
+                assert np.array_equal(bl.populations(), f0)
         b.run(steps, use_graph=use_graph)
     ms, launches, graphs = b.last_time()
     print(f"batch ms={ms:.3f} launches={launches} graph_launches={graphs}", flush=True)
@@ -94,6 +99,20 @@ def test_batch_periodic_matches_solo_fp32(use_graph):
     print(f"case batch periodic fp32 graph={use_graph}", flush=True)
     cs = [_drop_case(64, 1), _drop_case(96, 2), _drop_case(40, 3), _drop_case(130, 4)]
     _run_pair(cs, [20, 45, 9, 30], 1, use_graph)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("waves", [1, 2])
+def test_batch_waves_and_graph_reuse_match_solo(precision, waves):
+    """Droplet-vaporisation lattices (energy equation, Dirichlet ring) with
+    one or two waves per strip in the batched launch, three runs of the same
+    schedule (the second and third replay the graphs kept from the first,
+    with the solo lattices' eager steps in between), the last two prepared
+    ahead: every run bit-identical to stepping each lattice alone."""
+    print(f"case batch waves={waves} precision={precision} graph reuse", flush=True)
+    cs = [_drop_case(64, 1), _drop_case(96, 2), _drop_case(130, 4)]
+    _run_pair(cs, [24, 24, 24], precision, True, tiles=[5, 6, 8], runs=3, waves=waves,
+              prepare=True)
 
 
 def test_batch_single_lattice_long_graph_replay():
