@@ -50,7 +50,11 @@ typedef enum {
   LBM_E_HIP = 3,         /* HIP runtime error (text in lbm_last_error) */
   LBM_E_STATE = 4,       /* call out of order (e.g. step before init) */
   LBM_E_DOMAIN = 5,      /* state left the EOS / pseudopotential domain */
-  LBM_E_UNSUPPORTED = 6  /* valid request the library does not implement */
+  LBM_E_UNSUPPORTED = 6, /* valid request the library does not implement */
+  /* range sentinels, never returned: every int32 value is an lbm_status, so
+   * lbm_status_string() may be given any code a caller holds */
+  LBM_STATUS_MIN_ = -0x7fffffff - 1,
+  LBM_STATUS_MAX_ = 0x7fffffff
 } lbm_status;
 
 enum { LBM_FP64 = 0, LBM_FP32_SHIFTED = 1 };          /* storage precision */

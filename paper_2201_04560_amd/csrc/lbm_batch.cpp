@@ -99,9 +99,10 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int32_t n, void* dev_buf, size
                             void* hip_stream, lbm_batch** out) {
   if (!out || !ctxs || n < 1 || n > kMaxGrids || !dev_buf) return LBM_E_INVAL;
   *out = nullptr;
+  for (int i = 0; i < n; ++i)
+    if (!ctxs[i]) return LBM_E_INVAL;
   const int fp32 = ctxs[0]->p.precision == LBM_FP32_SHIFTED, walls = ctxs[0]->p.walls;
   for (int i = 0; i < n; ++i) {
-    if (!ctxs[i]) return LBM_E_INVAL;
     if ((ctxs[i]->p.precision == LBM_FP32_SHIFTED) != bool(fp32) || ctxs[i]->p.walls != walls)
       return fail(ctxs[i], LBM_E_INVAL, "a batch needs one precision and one wall setting");
   }

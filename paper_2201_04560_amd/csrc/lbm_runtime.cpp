@@ -161,6 +161,7 @@ const char* lbm_status_string(lbm_status s) {
     case LBM_E_STATE: return "call out of order";
     case LBM_E_DOMAIN: return "state left the EOS / pseudopotential domain";
     case LBM_E_UNSUPPORTED: return "unsupported";
+    default: break;
   }
   return "unknown status";
 }
