@@ -17,14 +17,16 @@
 //   fm1  rho, j, psi from the stored state (pull-stream)
 //   fm2  F^m, Q (kappa term), u
 //   fm3  the RK2 stage temperature T*
-//   per RK stage, second then first: coef (the adjoint of the temperature
-//        boundary rule, whose Dirichlet bottom values accumulate into the
-//        gradient, then the local partials of K), gather (transposed
-//        stencils)
-//   ca   adjoint of the MRT collision with the forcing S and the C term,
-//        of u = (j + F/2)/rho and of the moments
+//   per RK stage, second then first, one kernel each (k_ea_stage): the
+//        adjoint of the temperature boundary rule (the Dirichlet bottom
+//        values accumulate into the gradient) and the local partials of K on
+//        the workgroup's tile plus a one-node ring into LDS, then the
+//        transposed stencils gathered from there; the first stage's kernel
+//        goes on with
+//   ca   the adjoint of the MRT collision with the forcing S and the C term,
+//        of u = (j + F/2)/rho and of the moments, gathering the adjoint of
+//        the pull-stream from what the previous reversed step wrote
 //   fa   adjoint of F^m and Q with respect to psi, then of psi(rho, T)
-//   sa   adjoint of the pull-stream
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -65,8 +67,7 @@ struct Geo {
 // float64 scratch fields, dense index y * nx + x
 enum Field {
   F_RHO, F_JX, F_JY, F_PSI, F_FX, F_FY, F_QXX, F_QYY, F_QXY, F_UX, F_UY, F_T, F_TS,
-  F_THAT, F_AM2, F_AM1, F_TSH, F_PHILOC,
-  F_CUX, F_CUY, F_C1, F_C2X, F_C2Y, F_C3, F_DX, F_DY,
+  F_THAT, F_AM2, F_AM1, F_TSH,
   F_RHOE, F_UXE, F_UYE,
   F_FXH, F_FYH, F_QXXH, F_QYYH, F_QXYH, F_PSIS,
   // two sets (reversed steps alternate): adjoints of rho through psi and of
@@ -254,18 +255,32 @@ __device__ __forceinline__ double ea_mask(const double* __restrict__ gin, double
   return a;
 }
 
-// the mask, then the local partials of w * K(phi) at x, w = wfac * am(x),
-// in one kernel (am is a local map of gin)
-template <bool FIRST>
-__global__ __launch_bounds__(kThreads) void k_ea_coef(const double* __restrict__ gin, double* __restrict__ am,
-                                                      double* __restrict__ grad, BC bc,
-                                                      const double* __restrict__ phi_arr, double wfac, Geo g,
-                                                      Phys ph, Fields F) {
-  NODE_LOOP;
+// value of the mask at (x, y) (ea_mask without its side effects)
+__device__ __forceinline__ double ea_mask_val(const double* __restrict__ gin, const Geo& g, const BC& bc, int id,
+                                              int x, int y) {
+  const int k = kind_at(bc, x, y, g.nx, g.ny);
+  double a = 0.0;
+  if (k == T_FREE) {
+    a = gin[id];
+    if (y == 1 && kind_at(bc, x, 0, g.nx, g.ny) == T_ADIABATIC) a += gin[x];
+    if (y == g.ny - 2 && kind_at(bc, x, g.ny - 1, g.nx, g.ny) == T_ADIABATIC) a += gin[(g.ny - 1) * g.nx + x];
+  }
+  return a;
+}
+
+// coefficients of the local partials of w * K(phi) at one node that its
+// neighbours' transposed stencils gather
+struct EaCoef {
+  double cux, cuy, c1, c2x, c2y, c3, dx, dy;
+};
+// the local partials of w * K(phi) at (x, y): the gathered coefficients, and
+// the node's own terms (philoc: d/dphi(x); rl, uxl, uyl: d/drho, d/du)
+__device__ __forceinline__ void ea_coef_at(double w, const double* __restrict__ phi_arr, const Geo& g,
+                                           const Phys& ph, const Fields& F, int id, int x, int y, EaCoef& c,
+                                           double& philoc, double& rl, double& uxl, double& uyl) {
   const double* rho = F.f[F_RHO];
   const double* ux = F.f[F_UX];
   const double* uy = F.f[F_UY];
-  const double w = wfac * ea_mask(gin, am, grad, g, bc, id, x, y);
   const double p0 = phi_arr[id];
   double gx = 0, gy = 0, lap = 0, grx = 0, gry = 0, du = 0;
   #pragma unroll
@@ -286,56 +301,20 @@ __global__ __launch_bounds__(kThreads) void k_ea_coef(const double* __restrict__
   const double glx = ph.dlam * grx, gly = ph.dlam * gry;
   double gg, gT, gr;
   g_tdpdt(r, p0, ph, gg, gT, gr);
-  F.f[F_CUX][id] = w * ux[id];
-  F.f[F_CUY][id] = w * uy[id];
-  F.f[F_C1][id] = w * lam * rcv;
-  F.f[F_C2X][id] = w * glx * rcv;
-  F.f[F_C2Y][id] = w * gly * rcv;
-  F.f[F_C3][id] = w * gg * rcv;
-  F.f[F_DX][id] = w * gx * rcv;
-  F.f[F_DY][id] = w * gy * rcv;
+  c.cux = w * ux[id];
+  c.cuy = w * uy[id];
+  c.c1 = w * lam * rcv;
+  c.c2x = w * glx * rcv;
+  c.c2y = w * gly * rcv;
+  c.c3 = w * gg * rcv;
+  c.dx = w * gx * rcv;
+  c.dy = w * gy * rcv;
   // d lap / d phi(x) = -6 (1 - w_0)
-  F.f[F_PHILOC][id] = -6.0 * (1.0 - 4.0 / 9.0) * w * lam * rcv - w * gT * du * rcv;
+  philoc = -6.0 * (1.0 - 4.0 / 9.0) * w * lam * rcv - w * gT * du * rcv;
   const double num = lam * lap + glx * gx + gly * gy - gg * du;
-  const double rl = w * (-num * rcv / r + (ph.dlam * lap - gr * du) * rcv);
-  const double uxl = -w * gx, uyl = -w * gy;
-  if (FIRST) {
-    F.f[F_RHOE][id] = rl;
-    F.f[F_UXE][id] = uxl;
-    F.f[F_UYE][id] = uyl;
-  } else {
-    F.f[F_RHOE][id] += rl;
-    F.f[F_UXE][id] += uxl;
-    F.f[F_UYE][id] += uyl;
-  }
-}
-
-// transposed stencils: out = base1 + base2 + adjoint of phi
-__device__ __forceinline__ void ea_gather_at(double* __restrict__ out, const double* __restrict__ base1,
-                                             const double* __restrict__ base2, const Geo& g, const Phys& ph,
-                                             const Fields& F, int id, int x, int y) {
-  double ph_ = F.f[F_PHILOC][id], rh = 0, uxh = 0, uyh = 0;
-  #pragma unroll
-  for (int i = 1; i < 9; ++i) {
-    // x_src = y - c_i sees this node as its neighbour i
-    const int n = wrapi(y - d_cy[i], g.ny) * g.nx + wrapi(x - d_cx[i], g.nx);
-    const double cx = d_cx[i], cy = d_cy[i], W = d_wi[i];
-    ph_ += W * (-(F.f[F_CUX][n] * cx + F.f[F_CUY][n] * cy) + F.f[F_C2X][n] * cx + F.f[F_C2Y][n] * cy) +
-           6.0 * d_we[i] * F.f[F_C1][n];
-    rh += ph.dlam * W * (F.f[F_DX][n] * cx + F.f[F_DY][n] * cy);
-    uxh -= W * cx * F.f[F_C3][n];
-    uyh -= W * cy * F.f[F_C3][n];
-  }
-  F.f[F_RHOE][id] += rh;
-  F.f[F_UXE][id] += uxh;
-  F.f[F_UYE][id] += uyh;
-  out[id] = (base1 ? base1[id] : 0.0) + (base2 ? base2[id] : 0.0) + ph_;
-}
-__global__ __launch_bounds__(kThreads) void k_ea_gather(double* __restrict__ out, const double* __restrict__ base1,
-                                                        const double* __restrict__ base2, Geo g, Phys ph,
-                                                        Fields F) {
-  NODE_LOOP;
-  ea_gather_at(out, base1, base2, g, ph, F, id, x, y);
+  rl = w * (-num * rcv / r + (ph.dlam * lap - gr * du) * rcv);
+  uxl = -w * gx;
+  uyl = -w * gy;
 }
 
 // ----------------------------------------------------- collision adjoint
@@ -447,16 +426,90 @@ __global__ __launch_bounds__(kThreads) void k_ca(const S* __restrict__ P, Geo g,
   NODE_LOOP;
   ca_at(P, g, ph, F, thermal, set, seeded != 0, id, x, y);
 }
-// the first RK stage's transposed stencils and the collision adjoint in one
-// kernel: the latter reads only its own node's outputs of the former
-template <class S>
-__global__ __launch_bounds__(kThreads) void k_ea_gather_ca(const S* __restrict__ P, double* __restrict__ out,
-                                                           const double* __restrict__ base1,
-                                                           const double* __restrict__ base2, Geo g, Phys ph,
-                                                           Fields F, int set, int seeded) {
-  NODE_LOOP;
-  ea_gather_at(out, base1, base2, g, ph, F, id, x, y);
-  ca_at(P, g, ph, F, 1, set, seeded != 0, id, x, y);
+// Reversal of one RK stage in one kernel (periodic lattices): each workgroup
+// computes the local partials of its kEaTx x kEaTy tile and a one-node ring
+// around it into LDS (the ring's mask values are read, not written), then
+// every node of the tile gathers its neighbours' coefficients (the
+// transposed stencils).  Owned nodes keep the side effects: am, the
+// Dirichlet bottom entries of grad (one thread per column), the energy
+// equation's adjoints of rho and u (FIRST: the stage that starts them), and
+// out = base1 + (base2 or the node's own mask value) + the adjoint of phi.
+// CA: the collision adjoint of the node follows (it reads only the node's
+// own results of the stage).
+constexpr int kEaTx = 32, kEaTy = 8;
+template <bool FIRST, bool CA, class S>
+__global__ __launch_bounds__(kEaTx * kEaTy) void k_ea_stage(const S* __restrict__ P, const double* __restrict__ gin,
+                                                           double* __restrict__ am, double* __restrict__ grad,
+                                                           BC bc, const double* __restrict__ phi_arr, double wfac,
+                                                           double* __restrict__ out,
+                                                           const double* __restrict__ base1, int own_base2, Geo g,
+                                                           Phys ph, Fields F, int set, int seeded) {
+  constexpr int EX = kEaTx + 2, EY = kEaTy + 2, NE = EX * EY;
+  __shared__ double s_c[8][EY][EX];
+  const int t = threadIdx.x;
+  const int tx = t % kEaTx, ty = t / kEaTx;
+  const int x0 = blockIdx.x * kEaTx, y0 = blockIdx.y * kEaTy;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool owned = x < g.nx && y < g.ny;
+  const int id = owned ? y * g.nx + x : 0;
+  auto put = [&](int ex, int ey, const EaCoef& c) {
+    s_c[0][ey][ex] = c.cux;
+    s_c[1][ey][ex] = c.cuy;
+    s_c[2][ey][ex] = c.c1;
+    s_c[3][ey][ex] = c.c2x;
+    s_c[4][ey][ex] = c.c2y;
+    s_c[5][ey][ex] = c.c3;
+    s_c[6][ey][ex] = c.dx;
+    s_c[7][ey][ex] = c.dy;
+  };
+  double philoc = 0, rl = 0, uxl = 0, uyl = 0, a_own = 0;
+  if (owned) {
+    // the mask with its side effects (ea_mask), then the node's partials
+    a_own = ea_mask(gin, am, grad, g, bc, id, x, y);
+    EaCoef c;
+    ea_coef_at(wfac * a_own, phi_arr, g, ph, F, id, x, y, c, philoc, rl, uxl, uyl);
+    put(tx + 1, ty + 1, c);
+  }
+  // every other position of the extended tile: the ring around the tile
+  // and, in a tile cut by the lattice edge, the positions past the edge,
+  // which hold the periodic images (x0 - 1 + ex wrapped) that the edge
+  // nodes' stencils reach
+  for (int e = t; e < NE; e += kEaTx * kEaTy) {
+    const int ex = e % EX, ey = e / EX;
+    const int xu = x0 - 1 + ex, yu = y0 - 1 + ey;
+    if (ex >= 1 && ex <= kEaTx && ey >= 1 && ey <= kEaTy && xu < g.nx && yu < g.ny) continue;  // owned
+    const int xr = pmod(xu, g.nx), yr = pmod(yu, g.ny);
+    const int idr = yr * g.nx + xr;
+    EaCoef c;
+    double d0, d1, d2, d3;
+    ea_coef_at(wfac * ea_mask_val(gin, g, bc, idr, xr, yr), phi_arr, g, ph, F, idr, xr, yr, c, d0, d1, d2, d3);
+    put(ex, ey, c);
+  }
+  __syncthreads();
+  if (!owned) return;
+  // transposed stencils: the neighbour x - c_i sees this node as its i
+  double ph_ = philoc, rh = 0, uxh = 0, uyh = 0;
+  #pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const int ex = tx + 1 - d_cx[i], ey = ty + 1 - d_cy[i];
+    const double cx = d_cx[i], cy = d_cy[i], W = d_wi[i];
+    ph_ += W * (-(s_c[0][ey][ex] * cx + s_c[1][ey][ex] * cy) + s_c[3][ey][ex] * cx + s_c[4][ey][ex] * cy) +
+           6.0 * d_we[i] * s_c[2][ey][ex];
+    rh += ph.dlam * W * (s_c[6][ey][ex] * cx + s_c[7][ey][ex] * cy);
+    uxh -= W * cx * s_c[5][ey][ex];
+    uyh -= W * cy * s_c[5][ey][ex];
+  }
+  if (FIRST) {
+    F.f[F_RHOE][id] = rl + rh;
+    F.f[F_UXE][id] = uxl + uxh;
+    F.f[F_UYE][id] = uyl + uyh;
+  } else {
+    F.f[F_RHOE][id] += rl + rh;
+    F.f[F_UXE][id] += uxl + uxh;
+    F.f[F_UYE][id] += uyl + uyh;
+  }
+  out[id] = (base1 ? base1[id] : 0.0) + (own_base2 ? a_own : 0.0) + ph_;
+  if constexpr (CA) ca_at(P, g, ph, F, 1, set, seeded != 0, id, x, y);
 }
 
 // adjoint of F^m, Q with respect to psi (gather), then of psi(rho, T); the
@@ -667,24 +720,20 @@ static hipError_t recompute_step(const lbm_adjoint* a, const char* state, bool t
   return hipGetLastError();
 }
 
-// the reversed energy update of one step, F holding the step's forward
-// quantities
+// the reversed energy update of one step up to its first RK stage, F
+// holding the step's forward quantities: stage 2 (T' = BC(T + K(T*)))
+// reversed in one kernel; stage 1 is reversed together with the collision
+// in reverse_step_rest
+template <class S>
 static hipError_t reverse_energy(lbm_adjoint* a, bool thermal_on, const Fields& F) {
   const Geo& g = a->g;
   const Phys& ph = a->c->ph;
   double* grad = reinterpret_cast<double*>(a->buf + a->off_grad);
   hipStream_t st = a->c->stream;
-  const int nodes = g.nx * g.ny;
-  const dim3 grid((nodes + kThreads - 1) / kThreads), blk(kThreads);
-  if (thermal_on) {
-    // stage 2: T' = BC(T + K(T*))
-    hipLaunchKernelGGL(k_ea_coef<true>, grid, blk, 0, st, F.f[F_THAT], F.f[F_AM2], grad, a->bc, F.f[F_TS], 1.0, g,
-                       ph, F);
-    hipLaunchKernelGGL(k_ea_gather, grid, blk, 0, st, F.f[F_TSH], nullptr, nullptr, g, ph, F);
-    // stage 1: T* = BC(T + K(T)/2)
-    hipLaunchKernelGGL(k_ea_coef<false>, grid, blk, 0, st, F.f[F_TSH], F.f[F_AM1], grad, a->bc, F.f[F_T], 0.5, g,
-                       ph, F);
-  }
+  const dim3 tiles((g.nx + kEaTx - 1) / kEaTx, (g.ny + kEaTy - 1) / kEaTy), tblk(kEaTx * kEaTy);
+  if (thermal_on)
+    hipLaunchKernelGGL((k_ea_stage<true, false, S>), tiles, tblk, 0, st, nullptr, F.f[F_THAT], F.f[F_AM2], grad,
+                       a->bc, F.f[F_TS], 1.0, F.f[F_TSH], nullptr, 0, g, ph, F, 0, 0);
   return hipGetLastError();
 }
 
@@ -694,15 +743,19 @@ static hipError_t reverse_step_rest(lbm_adjoint* a, const char* state, bool ther
   const S* P = reinterpret_cast<const S*>(state);
   const Geo& g = a->g;
   const Phys& ph = a->c->ph;
+  double* grad = reinterpret_cast<double*>(a->buf + a->off_grad);
   hipStream_t st = a->c->stream;
   const int nodes = g.nx * g.ny;
   const dim3 grid((nodes + kThreads - 1) / kThreads), blk(kThreads);
+  const dim3 tiles((g.nx + kEaTx - 1) / kEaTx, (g.ny + kEaTy - 1) / kEaTy), tblk(kEaTx * kEaTy);
   // j counts the reversed steps from 0: the first reads the seed, each later
   // one gathers what the previous one wrote into the other set
   const int set = int(j & 1), seeded = j == 0;
   if (thermal_on)
-    hipLaunchKernelGGL(k_ea_gather_ca<S>, grid, blk, 0, st, P, F.f[F_THAT], F.f[F_AM2], F.f[F_AM1], g, ph, F, set,
-                       seeded);
+    // stage 1 (T* = BC(T + K(T)/2)) and the collision: the adjoint of T is
+    // that of stage 2's mask, of stage 1's mask and of phi
+    hipLaunchKernelGGL((k_ea_stage<false, true, S>), tiles, tblk, 0, st, P, F.f[F_TSH], F.f[F_AM1], grad, a->bc,
+                       F.f[F_T], 0.5, F.f[F_THAT], F.f[F_AM2], 1, g, ph, F, set, seeded);
   else
     hipLaunchKernelGGL(k_ca<S>, grid, blk, 0, st, P, g, ph, F, 0, set, seeded);
   hipLaunchKernelGGL(k_fa, grid, blk, 0, st, g, ph, F, set);
@@ -894,7 +947,7 @@ static lbm_status adj_backward(lbm_adjoint* a, double dJ, double* grad_host) {
       const bool th = c->p.thermal && n >= c->p.n_iso;
       const char* state = state_of(k, s);
       const Fields F = a->fields_at(k, s);
-      HIP_TRY(c, reverse_energy(a, th, F));
+      HIP_TRY(c, reverse_energy<S>(a, th, F));
       HIP_TRY(c, reverse_step_rest<S>(a, state, th, a->start_step + a->nsteps - 1 - n, F));
     }
     HIP_TRY(c, hipEventRecord(a->ev_reversed[k & 1], c->stream));
