@@ -485,6 +485,46 @@ def test_vaporisation512_full_size_bench_launch(precision):
         assert _rel(r, ro) < 1e-4 and _rel(T2, To) < 1e-6
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_vaporisation512x4_batched_bench_launch(precision):
+    """The metric's step as the bench times it: the four seeds (0-3) of the
+    512 x 512 vaporisation workload in one batched launch per step (13-row
+    strips, two waves per strip, graph-replayed), 20 steps; every lattice
+    against the oracle element by element over the whole lattice."""
+    print(f"case vaporisation512x4 batched precision={precision}", flush=True)
+    from paper_2201_04560_amd import Batch
+
+    eos, Tsat, rv, rl = cases.coexistence()
+    Tout = 0.95 * eos.Tc
+    n = 512
+    c = dict(nx=n, ny=n, a=2.0 / 49.0, sigma=0.1, kappa=0.1, rho_l=rl, rho_v=rv, thermal=True,
+             cv=6.0, lambda_l=2 / 3, lambda_v=2 / 3, t_side_dirichlet=True, t_side_val=Tout,
+             t_bottom_kind=np.full(n, 1), t_bottom_val=np.full(n, Tout),
+             t_top_kind=np.full(n, 1), t_top_val=np.full(n, Tout), **cases.wl.DROPLET_RATES)
+    inits = [cases.wl.droplet(n, n, 60.0, 4.6 / 5.0, rl, rv, Tsat, Tout, seed=sd) for sd in range(4)]
+    lats = []
+    for rho, T in inits:
+        lat = _lat(c, precision=precision, tile_y=13, strip_waves=2)
+        lat.init_fields(rho, None, None, T)
+        lats.append(lat)
+    b = Batch(lats)
+    b.prepare([20] * 4)
+    b.run([20] * 4)
+    for sd, ((rho, T), lat) in enumerate(zip(inits, lats)):
+        s = _oracle(c, rho, None, None, T)
+        s.step(20)
+        if precision == 0:
+            _compare(lat, s, 1e-11, f"vaporisation512 seed {sd} batched@20")
+        else:
+            r, _, _, T2 = lat.fields()
+            ro, _, _, To = s.fields()
+            print(f"seed {sd} fp32 rho rel", _rel(r, ro), "T rel", _rel(T2, To), flush=True)
+            assert _rel(r, ro) < 1e-4 and _rel(T2, To) < 1e-6
+    b.close()
+    for lat in lats:
+        lat.close()
+
+
 def test_fp32_vaporisation512_error_bound():
     """The stated accuracy of the benchmark's float32 step: the 512^2
     vaporisation workload after 2000 steps in float32 shifted storage
