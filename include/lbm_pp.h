@@ -297,6 +297,20 @@ lbm_status lbm_fit_sigma(double a, double b, double R, double omega, double G, d
  * continuum profile of the normal balance. */
 lbm_status lbm_planar_gamma(double a, double b, double R, double omega, double G, double T,
                             double sigma, double* gamma0);
+/* Latent heat of vaporisation h_fg of the EOS at temperature T (Sec. 4.2,
+ * the h_fg of Eq. stefan-analytical and of the Jakob number Ja =
+ * c_v (T_w - T_sat) / h_fg): the integral of T (dp/dT)_rho / rho^2 over
+ * [rho_v, rho_l], evaluated in closed form for Eq. peng-robinson.  rho_v,
+ * rho_l: the coexistence densities at T (lbm_pr_maxwell).  LBM_E_INVAL for
+ * non-positive a, b, R or T, T >= T_c, rho_l <= rho_v <= 0, b rho_l >= 1, a
+ * null h_fg or a non-finite result. */
+lbm_status lbm_pr_latent_heat(double a, double b, double R, double omega, double T, double rho_v,
+                              double rho_l, double* h_fg);
+/* beta of Eq. stefan-analytical: the root of
+ * sqrt(pi) beta exp(beta^2) erf(beta) = Ja (Ja = c_v (T_w - T_sat) / h_fg >= 0),
+ * by bisection to the last bits.  LBM_E_INVAL for a negative or non-finite
+ * Ja or a null beta. */
+lbm_status lbm_stefan_beta(double ja, double* beta);
 
 /* ---- reverse mode: heater-profile gradient (Sec. 2 step, Sec. 4) --------
  * Objective: evaporated liquid mass J = M_l(start) - M_l(end) over nsteps

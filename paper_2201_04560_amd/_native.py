@@ -97,6 +97,8 @@ SIGNATURES = [
     ("lbm_fit_sigma", c_int32, [c_double, c_double, c_double, c_double, c_double, c_double, _DP]),
     ("lbm_planar_gamma", c_int32, [c_double, c_double, c_double, c_double, c_double, c_double,
                                    c_double, _DP]),
+    ("lbm_pr_latent_heat", c_int32, [c_double] * 7 + [_DP]),
+    ("lbm_stefan_beta", c_int32, [c_double, _DP]),
 ]
 
 _lib = None

@@ -1,7 +1,8 @@
 // Host parameter pipeline of the mesh-refinement procedure (Sec. 3):
 // Peng-Robinson critical temperature, Maxwell coexistence, the sigma fit of
 // Eq. integral_coexistence_curve and the planar surface tension of
-// Eq. surface_tension.  Plain float64 C++, no GPU.
+// Eq. surface_tension; the latent heat and the Stefan constant of
+// Eq. stefan-analytical (Sec. 4.2).  Plain float64 C++, no GPU.
 #include <cmath>
 #include <functional>
 
@@ -26,6 +27,11 @@ struct PR {
   double dp(double rho, double T) const {
     const double br = b * rho, D = 1.0 + 2.0 * br - br * br;
     return R * T / ((1.0 - br) * (1.0 - br)) - a * alpha(T) * 2.0 * rho * (1.0 + br) / (D * D);
+  }
+  // d alpha / dT
+  double dalpha(double T) const {
+    const double s = 1.0 + kw * (1.0 - std::sqrt(T / Tc));
+    return -kw * s / std::sqrt(T * Tc);
   }
   // antiderivative of p dv in the specific volume v = 1/rho
   double int_p_dv(double v, double T) const {
@@ -118,6 +124,49 @@ extern "C" {
 
 double lbm_pr_critical_temperature(double a, double b, double R) {
   return 0.0778 * a / (0.45724 * b * R);
+}
+
+lbm_status lbm_pr_latent_heat(double a, double b, double R, double omega, double T, double rho_v,
+                              double rho_l, double* h_fg) {
+  if (!(a > 0) || !(b > 0) || !(R > 0) || !(T > 0) || !h_fg) return LBM_E_INVAL;
+  if (!(rho_v > 0) || !(rho_l > rho_v) || !(b * rho_l < 1.0)) return LBM_E_INVAL;
+  PR e(a, b, R, omega);
+  if (!(T < e.Tc)) return LBM_E_INVAL;
+  // h_fg = T int (dp/dT)_rho / rho^2 drho over [rho_v, rho_l], with
+  // (dp/dT)_rho = rho R / (1 - b rho) - a alpha'(T) rho^2 / (1 + 2 b rho - b^2 rho^2):
+  // the first part integrates to R ln(rho / (1 - b rho)), the second, with
+  // 1 + 2 b rho - b^2 rho^2 = 2 - (b rho - 1)^2, to
+  // ln((sqrt2 + b rho - 1) / (sqrt2 - b rho + 1)) / (2 sqrt2 b)
+  const double s2 = std::sqrt(2.0);
+  auto F = [&](double r) {
+    const double w = b * r - 1.0;
+    return R * std::log(r / (1.0 - b * r)) -
+           a * e.dalpha(T) * std::log((s2 + w) / (s2 - w)) / (2.0 * s2 * b);
+  };
+  const double h = T * (F(rho_l) - F(rho_v));
+  if (!std::isfinite(h)) return LBM_E_INVAL;
+  *h_fg = h;
+  return LBM_OK;
+}
+
+lbm_status lbm_stefan_beta(double ja, double* beta) {
+  if (!(ja >= 0.0) || !std::isfinite(ja) || !beta) return LBM_E_INVAL;
+  // g(beta) = sqrt(pi) beta exp(beta^2) erf(beta) rises from 0 and exceeds
+  // any finite Ja before beta = 6 (g(6) > 1e16)
+  const double sp = std::sqrt(M_PI);
+  auto g = [&](double x) { return sp * x * std::exp(x * x) * std::erf(x) - ja; };
+  double lo = 0.0, hi = 1.0;
+  while (g(hi) < 0.0) {
+    lo = hi;
+    hi *= 2.0;
+    if (hi > 64.0) return LBM_E_INVAL;
+  }
+  for (int i = 0; i < 200 && hi - lo > 1e-17 * hi; ++i) {
+    const double mid = 0.5 * (lo + hi);
+    if (g(mid) < 0.0) lo = mid; else hi = mid;
+  }
+  *beta = 0.5 * (lo + hi);
+  return LBM_OK;
 }
 
 lbm_status lbm_pr_maxwell(double a, double b, double R, double omega, double T, double* rho_v,

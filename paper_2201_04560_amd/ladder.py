@@ -12,7 +12,8 @@ import json
 import os
 import tempfile
 
-from .sim import make_params, refinement_level
+from .sim import make_params, refinement_level, stefan_beta
+from .sim import pr_latent_heat as _pr_latent_heat
 
 B_EOS, OMEGA = 2.0 / 21.0, 0.344
 
@@ -718,36 +719,9 @@ def stefan_front(rho_col, rho_l, rho_v):
 
 
 def pr_latent_heat(lv, a, b=2.0 / 21.0, R=1.0, omega=0.344):
-    """Latent heat h_fg at the level's T_sat from the Peng-Robinson EOS:
-    the integral of T (dp/dT)_rho / rho^2 over [rho_v, rho_l] (64-point
-    Gauss-Legendre)."""
-    import math
-
-    import numpy as np
-
-    kw_ = 0.37464 + 1.54226 * omega - 0.2699 * omega * omega
-    Tc, T = lv["Tc"], lv["T"]
-    sa = 1.0 + kw_ * (1.0 - math.sqrt(T / Tc))
-    dalpha = -kw_ * sa / math.sqrt(T * Tc)  # d alpha / dT
-    xg, wg = np.polynomial.legendre.leggauss(64)
-    r = 0.5 * (lv["rho_l"] + lv["rho_v"]) + 0.5 * (lv["rho_l"] - lv["rho_v"]) * xg
-    dpdT = r * R / (1.0 - b * r) - a * dalpha * r * r / (1.0 + 2.0 * b * r - (b * r) ** 2)
-    return float(0.5 * (lv["rho_l"] - lv["rho_v"]) * (wg * T * dpdT / (r * r)).sum())
-
-
-def stefan_beta(ja):
-    """beta of Eq. stefan-analytical: beta exp(beta^2) erf(beta) = Ja / sqrt(pi)
-    (bisection)."""
-    import math
-
-    lo, hi = 0.0, 5.0
-    for _ in range(200):
-        mid = 0.5 * (lo + hi)
-        if mid * math.exp(mid * mid) * math.erf(mid) * math.sqrt(math.pi) < ja:
-            lo = mid
-        else:
-            hi = mid
-    return 0.5 * (lo + hi)
+    """Latent heat h_fg at the level's T_sat between its Maxwell densities
+    (the library's closed form for the EOS)."""
+    return _pr_latent_heat(a, lv["T"], lv["rho_v"], lv["rho_l"], b=b, R=R, omega=omega)
 
 
 def stefan_refinement(meshes=(160, 320, 640, 1280, 2560), sets=(1, 2), L0=160, steps0=40000,

@@ -303,6 +303,21 @@ def planar_gamma(a, T, sigma, b=2.0 / 21.0, R=1.0, omega=0.344, G=-1.0):
     return g.value
 
 
+def pr_latent_heat(a, T, rho_v, rho_l, b=2.0 / 21.0, R=1.0, omega=0.344):
+    """Latent heat h_fg at T between the coexistence densities (Sec. 4.2)."""
+    h = ctypes.c_double()
+    check(lib().lbm_pr_latent_heat(a, b, R, omega, T, rho_v, rho_l, ctypes.byref(h)), None,
+          "lbm_pr_latent_heat")
+    return h.value
+
+
+def stefan_beta(ja):
+    """beta of Eq. stefan-analytical for the Jakob number ja."""
+    v = ctypes.c_double()
+    check(lib().lbm_stefan_beta(ja, ctypes.byref(v)), None, "lbm_stefan_beta")
+    return v.value
+
+
 def refinement_level(a_base, dx, Tr=0.86, kappa0=0.0, gy0=0.0, steps0=0, b=2.0 / 21.0, R=1.0,
                      omega=0.344, G=-1.0):
     """Parameters of a mesh dx times the base spacing (Sec. 3): a, T_c, T,

@@ -148,6 +148,14 @@ int main() {
   EXPECT(lbm_pr_maxwell(a, b, 1.0, 0.344, 1.01 * Tc, &rv, &rl, &ps) != LBM_OK);
   EXPECT(lbm_fit_sigma(a, b, 1.0, 0.344, -1.0, 0.86 * Tc, &sg) == LBM_OK && sg > 0.1 && sg < 0.12);
   EXPECT(lbm_planar_gamma(a, b, 1.0, 0.344, -1.0, 0.86 * Tc, sg, &g0) == LBM_OK && g0 > 0.0);
+  double hfg = 0, beta = 0;
+  EXPECT(lbm_pr_maxwell(a, b, 1.0, 0.344, 0.86 * Tc, &rv, &rl, &ps) == LBM_OK);
+  EXPECT(lbm_pr_latent_heat(a, b, 1.0, 0.344, 0.86 * Tc, rv, rl, &hfg) == LBM_OK && hfg > 0.0);
+  EXPECT(lbm_pr_latent_heat(a, b, 1.0, 0.344, 0.86 * Tc, rl, rv, &hfg) == LBM_E_INVAL);
+  EXPECT(lbm_pr_latent_heat(a, b, 1.0, 0.344, 0.86 * Tc, rv, rl, nullptr) == LBM_E_INVAL);
+  EXPECT(lbm_stefan_beta(0.038, &beta) == LBM_OK && beta > 0.1 && beta < 0.2);
+  EXPECT(lbm_stefan_beta(-1.0, &beta) == LBM_E_INVAL);
+  EXPECT(lbm_stefan_beta(1e300, &beta) == LBM_OK && beta > 20.0 && beta < 30.0);
   for (int m = 0; m <= 5; ++m) {
     lbm_level lv;
     const double dx = std::ldexp(1.0, -m);

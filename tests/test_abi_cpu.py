@@ -113,6 +113,29 @@ def test_host_parameter_pipeline_matches_oracle(lib, a):
     assert abs(pp.fit_sigma(a, T) - s) < 1e-10
     g = th.planar_gamma_continuum(eos, T, s)
     assert abs(pp.planar_gamma(a, T, s) / g - 1) < 1e-7
+    # Sec. 4.2: the library's closed-form h_fg against the oracle's quadrature
+    h = th.latent_heat(eos, T, (rv, rl, ps))
+    assert abs(pp.pr_latent_heat(a, T, rv, rl) / h - 1) < 1e-10
+
+
+def test_stefan_beta_and_latent_heat_rejections(lib):
+    """beta of Eq. stefan-analytical from the library against the oracle's
+    bisection over the Jakob numbers of Sec. 4.2 and beyond; invalid inputs
+    are refused."""
+    import paper_2201_04560_amd as pp
+    from paper_2201_04560_amd import LbmError
+
+    for ja in (0.0, 1e-4, 0.038, 0.076, 0.133, 0.5, 3.0, 40.0):
+        assert abs(pp.stefan_beta(ja) - th.stefan_beta(ja)) < 1e-12 * max(1.0, th.stefan_beta(ja))
+    for bad in (-1e-3, float("nan"), float("inf")):
+        with pytest.raises(LbmError):
+            pp.stefan_beta(bad)
+    a = 2.0 / 49.0
+    T = 0.86 * pp.pr_critical_temperature(a)
+    rv, rl, _ = pp.pr_maxwell(a, T)
+    for args in ((a, T, rl, rv), (a, T, 0.0, rl), (a, 1.01 * T / 0.86, rv, rl), (a, T, rv, 11.0)):
+        with pytest.raises(LbmError):
+            pp.pr_latent_heat(*args)
 
 
 def test_refinement_levels_match_oracle(lib):
