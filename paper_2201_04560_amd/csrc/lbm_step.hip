@@ -1171,7 +1171,8 @@ void lbm_march_multi_kernel(const StepArgs<S, C>* __restrict__ desc, const int* 
   int g = 0;
   while (g + 1 < ngrid && b >= start[g + 1]) ++g;
   const MacroOut O{};
-  march_body<S, C, WM, THERMAL, MODE_STEP, 1, false, true>(desc[g], O, b - start[g]);
+  const StepArgs<S, C> a = desc[g];  // see lbm_march2_multi_kernel
+  march_body<S, C, WM, THERMAL, MODE_STEP, 1, false, true>(a, O, b - start[g]);
 }
 
 // the batched launch with two waves per strip (energy step; see march_body)
@@ -1183,7 +1184,12 @@ void lbm_march2_multi_kernel(const StepArgs<S, C>* __restrict__ desc, const int*
   int g = 0;
   while (g + 1 < ngrid && b >= start[g + 1]) ++g;
   const MacroOut O{};
-  march_body<S, C, WM, true, MODE_STEP, 1, true, true>(desc[g], O, b - start[g]);
+  // a copy of the lattice's arguments: read through desc they were loaded
+  // again at their uses inside the row loop (322 scalar loads, each with a
+  // wait that also drains the LDS queue; 22 with the copy): 4 x 512^2
+  // float32 27.5 -> 26.9 us per step on MI355X
+  const StepArgs<S, C> a = desc[g];
+  march_body<S, C, WM, true, MODE_STEP, 1, true, true>(a, O, b - start[g]);
 }
 
 // ------------------------------------------------------------- launchers
