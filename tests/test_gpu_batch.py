@@ -115,6 +115,31 @@ def test_batch_waves_and_graph_reuse_match_solo(precision, waves):
               prepare=True)
 
 
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_back_to_back_schedules_match_solo(use_graph):
+    """Runs with different schedules queued one after another with no
+    synchronisation between them: each plan rewrites the device tables that
+    the previous run's launches read, so its uploads must wait for the work
+    already queued on the batch's stream.  Bit-identical to solo stepping."""
+    from paper_2201_04560_amd import Batch
+
+    print(f"case batch back-to-back schedules graph={use_graph}", flush=True)
+    cs = [_drop_case(64, 1), _drop_case(96, 2), _drop_case(40, 3)]
+    runs = [[30, 10, 20], [5, 25, 15], [12, 12, 12], [40, 0, 9]]
+    solo = [_make(c, 1) for c in cs]
+    grouped = [_make(c, 1) for c in cs]
+    b = Batch(grouped)
+    for steps in runs:
+        b.run(steps, use_graph=use_graph)
+    for lat, n in zip(solo, np.sum(runs, axis=0)):
+        lat.step(int(n))
+    for g, (a, bl) in enumerate(zip(solo, grouped)):
+        assert bl.step_count == a.step_count
+        assert np.array_equal(a.populations(), bl.populations()), g
+        assert np.array_equal(a.fields()[3], bl.fields()[3]), g
+    b.close()
+
+
 def test_batch_single_lattice_long_graph_replay():
     """One lattice, many steps: the replay path (repeated launch pairs)."""
     print("case batch single long", flush=True)
