@@ -154,11 +154,28 @@ def tune_vap_batch(tune, precision, seeds=SEEDS):
                            waves=(1, 2), with_waves=True)
 
 
-def run_vap_batch(precision, warmup, steps, tile_y, waves, seeds=SEEDS, want_fields=True):
+def pick_launch_mode(precision, tile_y, waves, seeds=SEEDS, steps=200):
+    """Graph replay or direct launches for the batched step: the faster of
+    the two over `steps` steps on throwaway lattices (on MI355X with ROCm 7
+    the graph-replayed launches ran about 1 % slower than direct ones for
+    this 25 us kernel; graphs pay off where launches are shorter than their
+    host cost, as on the small meshes of the refinement ladder)."""
+    best = None
+    for use_graph in (True, False):
+        r = run_vap_batch(precision, 20, steps, tile_y, waves, seeds, want_fields=False,
+                          use_graph=use_graph)
+        if best is None or r["wall_s"] < best[1]:
+            best = (use_graph, r["wall_s"])
+    return best[0]
+
+
+def run_vap_batch(precision, warmup, steps, tile_y, waves, seeds=SEEDS, want_fields=True,
+                  use_graph=True):
     """The seeds advanced together: one multi-lattice launch per step,
-    repeated launch pairs replayed from a captured graph.  Host wall clock
-    around the timed run; the batch's HIP events (recorded on its stream
-    around the same launches) give the kernel's average launch duration."""
+    repeated launch pairs replayed from a captured graph (use_graph) or
+    launched one by one.  Host wall clock around the timed run; the batch's
+    HIP events (recorded on its stream around the same launches) give the
+    kernel's average launch duration."""
     import torch
 
     from paper_2201_04560_amd import Batch
@@ -167,17 +184,18 @@ def run_vap_batch(precision, warmup, steps, tile_y, waves, seeds=SEEDS, want_fie
     b = Batch(lats)
     n = len(lats)
     if warmup:
-        b.run([warmup] * n)
-    # tables and graphs of the timed schedule set up ahead (no launch)
-    b.prepare([steps] * n)
+        b.run([warmup] * n, use_graph=use_graph)
+    # tables (and graphs) of the timed schedule set up ahead (no launch)
+    b.prepare([steps] * n, use_graph=use_graph)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    b.run([steps] * n)
+    b.run([steps] * n, use_graph=use_graph)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms, launches, graphs = b.last_time()
     out = dict(wall_s=wall, ev_ms=ms, kernel_ms_avg=ms / max(launches, 1), launches=launches,
-               graph_launches=graphs, tile_y=lats[0].tile_y, strip_waves=lats[0].strip_waves)
+               graph_launches=graphs, tile_y=lats[0].tile_y, strip_waves=lats[0].strip_waves,
+               use_graph=use_graph)
     if want_fields:
         out["fields"] = [lat.fields() for lat in lats]
         out["norms"] = [lat.norms() for lat in lats]
@@ -768,6 +786,9 @@ def main():
                          "precisions")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--tile-y", type=int, default=0)
+    ap.add_argument("--launch", choices=["auto", "graph", "direct"], default="auto",
+                    help="batched step: graph-replayed or direct launches (auto: the faster over "
+                         "200 steps)")
     ap.add_argument("--strip-waves", type=int, default=0,
                     help="waves per strip with --tile-y (0: the library's choice)")
     ap.add_argument("--traffic-from", default=None, metavar="DIR",
@@ -831,7 +852,8 @@ def main():
                 continue
             if args.profile_case == "vaporisation512x4":
                 ty, w = (args.tile_y, args.strip_waves) if args.tile_y else tune_vap_batch(tune, prec)
-                r = run_vap_batch(prec, args.warmup, args.steps, ty, w, want_fields=False)
+                ug = (args.launch == "graph") if args.launch != "auto" else pick_launch_mode(prec, ty, w)
+                r = run_vap_batch(prec, args.warmup, args.steps, ty, w, want_fields=False, use_graph=ug)
             else:
                 pcase = vaporisation_case() if args.profile_case == "vaporisation512" else pool_case()
                 r = run_lattice(pcase, prec, args.warmup, args.steps, want_fields=False,
@@ -859,9 +881,10 @@ def main():
         if name == "fp32":
             ty, w = (args.tile_y, args.strip_waves) if args.tile_y else tune_vap_batch(tune, prec)
             tiles[name] = (ty, w)
-            log(f"bench: fp32 4 x {nx}x{ny} vaporisation batch, tile_y {ty}, waves {w}, warmup "
-                f"{args.warmup}, steps {args.steps}")
-            res[name] = run_vap_batch(prec, args.warmup, args.steps, ty, w)
+            ug = (args.launch == "graph") if args.launch != "auto" else pick_launch_mode(prec, ty, w)
+            log(f"bench: fp32 4 x {nx}x{ny} vaporisation batch, tile_y {ty}, waves {w}, "
+                f"{'graph-replayed' if ug else 'direct'} launches, warmup {args.warmup}, steps {args.steps}")
+            res[name] = run_vap_batch(prec, args.warmup, args.steps, ty, w, use_graph=ug)
         else:
             log(f"bench: fp64 plain step, 4 x {nx}x{ny} one lattice after another, warmup "
                 f"{args.warmup}, steps {args.steps}")
@@ -897,7 +920,9 @@ def main():
                    "nx": nx, "ny": ny, "lattices": len(SEEDS),
                    "storage": "f32 shifted populations (f - w rho_v) + f32 T; f64 EOS/psi/forces "
                               "and reductions" if main_name == "fp32" else "f64",
-                   "launch": "one batched multi-lattice launch per step, graph-replayed"
+                   "launch": ("one batched multi-lattice launch per step, " +
+                              ("graph-replayed" if m.get("use_graph") else "launched directly") +
+                              (" (the faster of the two over 200 steps)" if args.launch == "auto" else ""))
                              if main_name == "fp32" else "one launch per lattice and step",
                    "steps_total": args.warmup + args.steps,
                    "tile_y": m["tile_y"], "strip_waves": m["strip_waves"]},
