@@ -1236,8 +1236,12 @@ void lbm_march_multi_kernel(const StepArgs<S, C>* __restrict__ desc, const int* 
   int g = 0;
   while (g + 1 < ngrid && b >= start[g + 1]) ++g;
   const MacroOut O{};
-  const StepArgs<S, C> a = desc[g];  // see lbm_march2_multi_kernel
-  march_body<S, C, WM, THERMAL, MODE_STEP, 1, false, true>(a, O, b - start[g]);
+  // arguments read through the table and plain (flat) accesses: unlike the
+  // two-wave kernel, this one ran slower with a local copy of the arguments
+  // and with global-address accesses (finest mesh of the pool ladder, 4 x
+  // 1024 x 2048 float32, 52-row strips: 213 us per step, 227 with the
+  // global accesses, 241 with the copy as well, on MI355X)
+  march_body<S, C, WM, THERMAL, MODE_STEP, 1, false, false>(desc[g], O, b - start[g]);
 }
 
 // the batched launch with two waves per strip (energy step; see march_body)
