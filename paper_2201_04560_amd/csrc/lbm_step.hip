@@ -1126,8 +1126,9 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
       }
     } else if (wave == 0) {
       // wave 0 carries the longer chain (pull, EOS, forces, collision): it
-      // goes first when waves of its SIMD compete for an issue slot (float64
-      // 512^2: 19.5 -> 18.6 us per step on MI355X; float32 unchanged)
+      // goes first when waves of its SIMD compete for an issue slot (on
+      // MI355X: float64 512^2 19.5 -> 18.6 us per step; batched 4 x 512^2
+      // float32 26.7 -> 25.5 us; priority 3 measured the same as 2)
       __builtin_amdgcn_s_setprio(2);
       auto w0 = [&](auto phc, const int k) {
         constexpr int PH = decltype(phc)::value;
