@@ -422,13 +422,15 @@ def test_domain_error_is_reported():
     assert ei.value.status == 5
 
 
-def test_fp32_shifted_tracks_fp64():
+@pytest.mark.parametrize("waves", [1, 2])
+def test_fp32_shifted_tracks_fp64(waves):
     """FP32 shifted storage: parity unpinned (reported); here only a loose
-    agreement with the oracle on the random walls case after 50 steps."""
-    print("case fp32 shifted", flush=True)
+    agreement with the oracle on the random walls case after 50 steps, with
+    one wave per strip (pointer accesses) and two (buffer accesses)."""
+    print(f"case fp32 shifted waves={waves}", flush=True)
     c, rho, ux, uy, T = cases.random_tiny(64, 32, seed=4, walls=True, thermal=True, gy=-1e-4)
     s = _oracle(c, rho, ux, uy, T)
-    lat = _lat(c, precision=1)
+    lat = _lat(c, precision=1, strip_waves=waves)
     lat.init_fields(rho, ux, uy, T)
     s.step(50)
     lat.step(50)
