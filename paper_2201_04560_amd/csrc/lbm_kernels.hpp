@@ -16,6 +16,9 @@ constexpr int kNormSlots = 12;
 inline bool two_wave_fits(long long plane, int elem, int ny) {
   return 9ll * plane * elem < (1ll << 32) && ny >= 3;
 }
+// the 9 population planes (and so the temperature plane) below 4 GiB: byte
+// offsets into them fit 32 bits (buffer accesses of the one-wave step)
+inline bool arrays_fit_32bit(long long plane, int elem) { return 9ll * plane * elem < (1ll << 32); }
 
 struct LaunchStep {
   int fp32;

@@ -239,7 +239,9 @@ __device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70)
 // GA: global-memory accesses name their address space (batched kernels,
 // see gld); the batched two-wave float32 step on 4 x 512^2 27.8 -> 27.3 us
 // on MI355X.
-template <class S, class C, int WM, bool THERMAL, int MODE, int RPI, bool WS, bool GA>
+// BUF1: the one-wave march accesses its arrays through buffer resources
+// (float32 storage, 9 planes below 4 GiB; chosen by the launcher).
+template <class S, class C, int WM, bool THERMAL, int MODE, int RPI, bool WS, bool GA, bool BUF1 = false>
 __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroOut& O, const int bid) {
   constexpr bool WALLS = WM != 0;
   // Newton steps of the float64 reciprocals and square roots: one is below
@@ -301,11 +303,14 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
                           ox + 5 * pb32, ox + 6 * pb32, ox + 7 * pb32, ox + 8 * pb32};
   // byte offset of row y >= 0 (OFF32: one 32-bit multiply)
   const uint32_t rb32 = uint32_t(row_b);
-  // BUF (float32 storage, two-wave march): the four arrays as buffer
-  // resources (9 planes, and the temperature's pitch x ny, below 4 GiB:
-  // checked by the launcher).  4 x 512^2 float32 26.3 -> 25.5 us per step on
-  // MI355X; float64 measured no faster (single lattice 1 % slower)
-  constexpr bool BUF = OFF32 && sizeof(S) == 4;
+  // BUF (float32 storage, two-wave march, or BUF1): the four arrays as
+  // buffer resources (9 planes, and the temperature's pitch x ny, below 4
+  // GiB: checked by the launcher).  On MI355X: two-wave 4 x 512^2 float32
+  // 26.3 -> 25.5 us per step, one-wave 4096^2 pool float32 429 -> 402 us;
+  // float64 measured no faster (single lattice 1 % slower), nor did the
+  // one-wave batched kernel (finest ladder mesh 214 -> 222 us)
+  static_assert(!BUF1 || (!WS && sizeof(S) == 4), "one-wave float32 buffer accesses only");
+  constexpr bool BUF = (OFF32 && sizeof(S) == 4) || BUF1;
   const uint32_t fbytes32 = uint32_t(9 * plane_b), tbytes32 = uint32_t(size_t(ny) * row_b);
   const rsrc_t rs_fin = make_rsrc(A.fin, fbytes32), rs_fout = make_rsrc(A.fout, fbytes32);
   const rsrc_t rs_Tin = make_rsrc(A.Tin, tbytes32), rs_Tout = make_rsrc(A.Tout, tbytes32);
@@ -371,7 +376,19 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
     const char* ru = fin + roff(yup);
     C v2, v5, v6, v4, v7, v8;
     const uint32_t oc = uint32_t(yr) * rb32;
-    if constexpr (BUF) {
+    if constexpr (BUF && !OFF32) {
+      // one-wave march: the plane offsets go into the SGPR offset
+      const uint32_t od = uint32_t(ydn) * rb32, ou = uint32_t(yup) * rb32;
+      gn[0] = C(bld(rs_fin, ox, oc));
+      gn[1] = C(bld(rs_fin, oxm, oc + pb32));
+      gn[3] = C(bld(rs_fin, oxp, oc + 3 * pb32));
+      v2 = C(bld(rs_fin, ox, od + 2 * pb32));
+      v5 = C(bld(rs_fin, oxm, od + 5 * pb32));
+      v6 = C(bld(rs_fin, oxp, od + 6 * pb32));
+      v4 = C(bld(rs_fin, ox, ou + 4 * pb32));
+      v7 = C(bld(rs_fin, oxp, ou + 7 * pb32));
+      v8 = C(bld(rs_fin, oxm, ou + 8 * pb32));
+    } else if constexpr (BUF) {
       const uint32_t od = uint32_t(ydn) * rb32, ou = uint32_t(yup) * rb32;
       gn[0] = C(bld(rs_fin, lo[0], oc));
       gn[1] = C(bld(rs_fin, lo[1], oc));
@@ -645,7 +662,9 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
       char* orow = fout + roff(ysu);
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        if constexpr (BUF)
+        if constexpr (BUF && !OFF32)
+          bstore(rs_fout, ox, uint32_t(ysu) * rb32 + uint32_t(i) * pb32, S(o[i]));
+        else if constexpr (BUF)
           bstore(rs_fout, so[i], uint32_t(ysu) * rb32, S(o[i]));
         else if constexpr (OFF32)
           st(orow, so[i], S(o[i]));
@@ -1210,10 +1229,10 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
   }
 }
 
-template <class S, class C, int WM, bool THERMAL, int MODE>
+template <class S, class C, int WM, bool THERMAL, int MODE, bool BUF1>
 __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(WavesPerEU<S>::value, 8)))
 void lbm_march_kernel(StepArgs<S, C> A, MacroOut O) {
-  march_body<S, C, WM, THERMAL, MODE, 1, false, false>(A, O, blockIdx.x);
+  march_body<S, C, WM, THERMAL, MODE, 1, false, false, BUF1>(A, O, blockIdx.x);
 }
 
 // the energy step with two waves per strip (see march_body)
@@ -1285,8 +1304,18 @@ static PhysC<C> phys_c(const Phys& p) {
 }
 
 template <class S, class C, int WM, bool THERMAL, int MODE>
-static void launch_one(const StepArgs<S, C>& a, const MacroOut& o, int nblocks, hipStream_t st) {
-  hipLaunchKernelGGL((lbm_march_kernel<S, C, WM, THERMAL, MODE>), dim3(nblocks), dim3(kLanes), 0,
+static void launch_one(const StepArgs<S, C>& a, const MacroOut& o, int nblocks, bool buf,
+                       hipStream_t st) {
+  // (the energy step only: the isothermal kernel with walls needed more
+  // registers with buffers, 121 -> 130 VGPRs, one wave per SIMD fewer)
+  if constexpr (sizeof(S) == 4 && MODE == MODE_STEP && THERMAL) {
+    if (buf) {
+      hipLaunchKernelGGL((lbm_march_kernel<S, C, WM, THERMAL, MODE, true>), dim3(nblocks), dim3(kLanes), 0,
+                         st, a, o);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((lbm_march_kernel<S, C, WM, THERMAL, MODE, false>), dim3(nblocks), dim3(kLanes), 0,
                      st, a, o);
 }
 
@@ -1297,10 +1326,11 @@ static int wall_mode(int walls, const Phys& ph) {
 }
 
 template <class S, class C, bool THERMAL, int MODE>
-static void launch_wm(int wm, const StepArgs<S, C>& a, const MacroOut& o, int nblocks, hipStream_t st) {
-  if (wm == 2) launch_one<S, C, 2, THERMAL, MODE>(a, o, nblocks, st);
-  else if (wm == 1) launch_one<S, C, 1, THERMAL, MODE>(a, o, nblocks, st);
-  else launch_one<S, C, 0, THERMAL, MODE>(a, o, nblocks, st);
+static void launch_wm(int wm, const StepArgs<S, C>& a, const MacroOut& o, int nblocks, bool buf,
+                      hipStream_t st) {
+  if (wm == 2) launch_one<S, C, 2, THERMAL, MODE>(a, o, nblocks, buf, st);
+  else if (wm == 1) launch_one<S, C, 1, THERMAL, MODE>(a, o, nblocks, buf, st);
+  else launch_one<S, C, 0, THERMAL, MODE>(a, o, nblocks, buf, st);
 }
 
 template <class S, class C>
@@ -1340,8 +1370,10 @@ static hipError_t launch_step_t(const LaunchStep& L, hipStream_t st, int mode) {
   MacroOut o{L.o_rho, L.o_ux, L.o_uy, L.o_T, L.o_f, L.f_first, L.f_count};
   const int nb = L.ntx * L.nty;
   const int wm = wall_mode(L.walls, L.ph);
+  // one-wave float32 step: buffer accesses where the 9 planes fit 4 GiB
+  const bool buf = L.fp32 && arrays_fit_32bit(L.plane, 4);
   if (mode == MODE_MACRO) {
-    launch_wm<S, C, false, MODE_MACRO>(wm, a, o, nb, st);
+    launch_wm<S, C, false, MODE_MACRO>(wm, a, o, nb, false, st);
   } else if (L.update_T && L.waves == 2 && two_wave_fits(L.plane, L.fp32 ? 4 : 8, L.ny)) {
     if (wm == 2)
       hipLaunchKernelGGL((lbm_march2_kernel<S, C, 2>), dim3(nb), dim3(2 * kLanes), 0, st, a);
@@ -1350,9 +1382,9 @@ static hipError_t launch_step_t(const LaunchStep& L, hipStream_t st, int mode) {
     else
       hipLaunchKernelGGL((lbm_march2_kernel<S, C, 0>), dim3(nb), dim3(2 * kLanes), 0, st, a);
   } else if (L.update_T) {
-    launch_wm<S, C, true, MODE_STEP>(wm, a, o, nb, st);
+    launch_wm<S, C, true, MODE_STEP>(wm, a, o, nb, buf, st);
   } else {
-    launch_wm<S, C, false, MODE_STEP>(wm, a, o, nb, st);
+    launch_wm<S, C, false, MODE_STEP>(wm, a, o, nb, false, st);
   }
   return hipGetLastError();
 }
