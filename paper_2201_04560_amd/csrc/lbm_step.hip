@@ -420,19 +420,30 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
       v7 = C(ld(ru + 7 * plane_b, oxp));
       v8 = C(ld(ru + 8 * plane_b, oxm));
     }
-    gn[2] = kdn ? v2 : C(0);
-    gn[5] = kdn ? v5 : C(0);
-    gn[6] = kdn ? v6 : C(0);
-    // zero-gradient outflow: the top row's populations from above are those
-    // of the row below, i.e. pulled from its own row (the clamped address)
-    const bool kin = kup || (WALLS && outflow);
-    gn[4] = kin ? v4 : C(0);
-    gn[7] = kin ? v7 : C(0);
-    gn[8] = kin ? v8 : C(0);
+    // beyond a wall the values are dropped by wall_mask where the row is
+    // consumed; the zero-gradient outflow keeps the top row's (the clamped
+    // address: its populations from above are pulled from its own row)
+    gn[2] = v2;
+    gn[5] = v5;
+    gn[6] = v6;
+    gn[4] = v4;
+    gn[7] = v7;
+    gn[8] = v8;
     if constexpr (BUF)
       Tn = C(bld(rs_Tin, ox, oc));
     else
       Tn = C(ld(Tin + roff(yr), ox));
+  };
+
+  // populations pulled from beyond a wall do not exist.  They are zeroed
+  // where the row is consumed, not where its loads are issued: a select
+  // next to the loads made the wave wait for its prefetched row at once
+  // (walled one-wave march, 4096^2 pool float32 on MI355X)
+  auto wall_mask = [&](const int r, C (&g)[9]) {
+    if constexpr (WALLS) {
+      if (r < 1) g[2] = g[5] = g[6] = C(0);
+      if (r + 1 >= ny && !outflow) g[4] = g[7] = g[8] = C(0);
+    }
   };
 
   uint32_t err = 0;
@@ -992,6 +1003,7 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
       Tr[j] = Tn[j];
 #pragma unroll
       for (int i = 0; i < 9; ++i) g[j][i] = gn[j][i];
+      wall_mask(r0 + j, g[j]);
     }
     if constexpr (DEFER) {
       wait_vmem();
@@ -1103,6 +1115,7 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
             C g[9], jx, jy, a1, a2;
 #pragma unroll
             for (int i = 0; i < 9; ++i) g[i] = gn[0][i];
+            wall_mask(r, g);
             const C Tr = Tn[0];
             if (r + 1 < rend) load_row(r + 1, gn[0], Tn[0]);
             stageA(sr, r, g, Tr, jx, jy, a1, a2);
