@@ -436,9 +436,17 @@ __global__ __launch_bounds__(kThreads) void k_ca(const S* __restrict__ P, Geo g,
 // out = base1 + (base2 or the node's own mask value) + the adjoint of phi.
 // CA: the collision adjoint of the node follows (it reads only the node's
 // own results of the stage).
+// The workgroup has a thread for each of the extended tile's positions: the
+// tile's own (or, in a tile cut by the lattice edge, their periodic images)
+// and the 84 of the ring, so that no thread evaluates two positions one
+// after the other (with one thread per tile node some evaluated three: the
+// 256^2 x 500-step backward took 19.1 ms float32 / 19.7 ms float64 on
+// MI355X, 18.0 / 18.5 ms with this layout; gradients bit-identical).
 constexpr int kEaTx = 32, kEaTy = 8;
+constexpr int kEaRing = 2 * (kEaTx + 2) + 2 * kEaTy;
+constexpr int kEaThreads = (kEaTx * kEaTy + kEaRing + 63) / 64 * 64;
 template <bool FIRST, bool CA, class S>
-__global__ __launch_bounds__(kEaTx * kEaTy) void k_ea_stage(const S* __restrict__ P, const double* __restrict__ gin,
+__global__ __launch_bounds__(kEaThreads) void k_ea_stage(const S* __restrict__ P, const double* __restrict__ gin,
                                                            double* __restrict__ am, double* __restrict__ grad,
                                                            BC bc, const double* __restrict__ phi_arr, double wfac,
                                                            double* __restrict__ out,
@@ -462,23 +470,40 @@ __global__ __launch_bounds__(kEaTx * kEaTy) void k_ea_stage(const S* __restrict_
     s_c[6][ey][ex] = c.dx;
     s_c[7][ey][ex] = c.dy;
   };
+  static_assert(kEaTx * kEaTy + kEaRing == NE, "extended tile = tile + ring");
   double philoc = 0, rl = 0, uxl = 0, uyl = 0, a_own = 0;
-  if (owned) {
+  const bool tile_thread = t < kEaTx * kEaTy;
+  if (tile_thread && owned) {
     // the mask with its side effects (ea_mask), then the node's partials
     a_own = ea_mask(gin, am, grad, g, bc, id, x, y);
     EaCoef c;
     ea_coef_at(wfac * a_own, phi_arr, g, ph, F, id, x, y, c, philoc, rl, uxl, uyl);
     put(tx + 1, ty + 1, c);
-  }
-  // every other position of the extended tile: the ring around the tile
-  // and, in a tile cut by the lattice edge, the positions past the edge,
-  // which hold the periodic images (x0 - 1 + ex wrapped) that the edge
-  // nodes' stencils reach
-  for (int e = t; e < NE; e += kEaTx * kEaTy) {
-    const int ex = e % EX, ey = e / EX;
-    const int xu = x0 - 1 + ex, yu = y0 - 1 + ey;
-    if (ex >= 1 && ex <= kEaTx && ey >= 1 && ey <= kEaTy && xu < g.nx && yu < g.ny) continue;  // owned
-    const int xr = pmod(xu, g.nx), yr = pmod(yu, g.ny);
+  } else if (t < NE) {
+    // another position of the extended tile: a tile position past the
+    // lattice edge (periodic image, x0 - 1 + ex wrapped) or one of the ring
+    // (q: bottom row, top row, left column, right column)
+    int ex, ey;
+    if (tile_thread) {
+      ex = tx + 1;
+      ey = ty + 1;
+    } else {
+      const int q = t - kEaTx * kEaTy;
+      if (q < EX) {
+        ex = q;
+        ey = 0;
+      } else if (q < 2 * EX) {
+        ex = q - EX;
+        ey = EY - 1;
+      } else if (q < 2 * EX + kEaTy) {
+        ex = 0;
+        ey = q - 2 * EX + 1;
+      } else {
+        ex = EX - 1;
+        ey = q - 2 * EX - kEaTy + 1;
+      }
+    }
+    const int xr = pmod(x0 - 1 + ex, g.nx), yr = pmod(y0 - 1 + ey, g.ny);
     const int idr = yr * g.nx + xr;
     EaCoef c;
     double d0, d1, d2, d3;
@@ -486,7 +511,7 @@ __global__ __launch_bounds__(kEaTx * kEaTy) void k_ea_stage(const S* __restrict_
     put(ex, ey, c);
   }
   __syncthreads();
-  if (!owned) return;
+  if (!tile_thread || !owned) return;
   // transposed stencils: the neighbour x - c_i sees this node as its i
   double ph_ = philoc, rh = 0, uxh = 0, uyh = 0;
   #pragma unroll
@@ -730,7 +755,7 @@ static hipError_t reverse_energy(lbm_adjoint* a, bool thermal_on, const Fields& 
   const Phys& ph = a->c->ph;
   double* grad = reinterpret_cast<double*>(a->buf + a->off_grad);
   hipStream_t st = a->c->stream;
-  const dim3 tiles((g.nx + kEaTx - 1) / kEaTx, (g.ny + kEaTy - 1) / kEaTy), tblk(kEaTx * kEaTy);
+  const dim3 tiles((g.nx + kEaTx - 1) / kEaTx, (g.ny + kEaTy - 1) / kEaTy), tblk(kEaThreads);
   if (thermal_on)
     hipLaunchKernelGGL((k_ea_stage<true, false, S>), tiles, tblk, 0, st, nullptr, F.f[F_THAT], F.f[F_AM2], grad,
                        a->bc, F.f[F_TS], 1.0, F.f[F_TSH], nullptr, 0, g, ph, F, 0, 0);
@@ -747,7 +772,7 @@ static hipError_t reverse_step_rest(lbm_adjoint* a, const char* state, bool ther
   hipStream_t st = a->c->stream;
   const int nodes = g.nx * g.ny;
   const dim3 grid((nodes + kThreads - 1) / kThreads), blk(kThreads);
-  const dim3 tiles((g.nx + kEaTx - 1) / kEaTx, (g.ny + kEaTy - 1) / kEaTy), tblk(kEaTx * kEaTy);
+  const dim3 tiles((g.nx + kEaTx - 1) / kEaTx, (g.ny + kEaTy - 1) / kEaTy), tblk(kEaThreads);
   // j counts the reversed steps from 0: the first reads the seed, each later
   // one gathers what the previous one wrote into the other set
   const int set = int(j & 1), seeded = j == 0;
