@@ -620,3 +620,60 @@ def test_pool_1024x2048_full_size_properties():
     e = _rel(r3, r1)
     print(f"fp32 vs fp64 rho rel {e:.2e}", flush=True)
     assert e < 1e-3
+
+
+def _slab(nx, ny, half, **over):
+    """A flat liquid slab of half-width `half` centred in a periodic nx x ny
+    lattice (droplet rates of Sec. 4.1), and its initial density."""
+    import workloads as wl
+
+    eos, T, rv, rl = cases.coexistence()
+    c = dict(nx=nx, ny=ny, a=2.0 / 49.0, sigma=0.1, kappa=0.0, rho_l=rl, rho_v=rv,
+             **wl.DROPLET_RATES)
+    c.update(over)
+    y = np.arange(ny)[:, None].astype(float) * np.ones((1, nx))
+    rho = wl.tanh_blend(np.abs(y - ny / 2), half, 0.5, rl, rv)
+    return c, rho, np.full_like(rho, T)
+
+
+def test_planar_interface_does_not_see_kappa():
+    """The kappa term adds nothing to the normal stress of a flat interface
+    (reading R13): with equal relaxation rates the float64 step gives the
+    same coexistence profile for kappa = 0 and 0.3 (the oracle's own pin,
+    here on the GPU at 64 x 256 over 3000 steps, several tiles and strips)."""
+    print("case planar kappa", flush=True)
+    prof = {}
+    for k in (0.0, 0.3):
+        c, rho, T = _slab(64, 256, 60, kappa=k)
+        lat = _lat(c)
+        lat.init_fields(rho, None, None, T)
+        lat.step(3000)
+        prof[k] = lat.fields()[0]
+        lat.close()
+    d = np.abs(prof[0.3] - prof[0.0]).max()
+    print(f"max |rho(0.3) - rho(0)| {d:.2e}", flush=True)
+    assert d < 1e-10
+
+
+def test_gravity_momentum_balance():
+    """Eq. gravitational_force on the GPU (float64): on a periodic lattice
+    the body forces sum to zero, so the total momentum stays zero to
+    rounding, and a liquid slab between vapour layers gains momentum along g
+    at g sum_liquid (rho - rho_bar): within 3 % after five steps."""
+    print("case gravity momentum", flush=True)
+    from oracle import lattice as olat
+
+    g = -2e-5
+    c, rho, T = _slab(64, 160, 30, gy=g, kappa=0.1)
+    lat = _lat(c)
+    lat.init_fields(rho, None, None, T)
+    lat.step(5)
+    f = lat.populations()
+    lat.close()
+    jy = np.tensordot(olat.CY.astype(float), f, 1)
+    liq = rho > 0.5 * (c["rho_l"] + c["rho_v"])
+    gain = g * (rho[liq] - rho.mean()).sum()
+    print(f"total {jy.sum():.2e}, liquid {jy[liq].sum() / (5 * gain):.4f} of 5 g sum(rho - rho_bar)",
+          flush=True)
+    assert abs(jy.sum()) < 1e-9 * abs(gain)
+    assert abs(jy[liq].sum() / (5 * gain) - 1) < 0.03

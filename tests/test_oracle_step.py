@@ -99,6 +99,100 @@ def test_collision_conserves_mass_and_adds_force(walls):
     np.testing.assert_allclose(m["ux"] * m["rho"], m["jx"] + 0.5 * m["fx"], atol=1e-14)
 
 
+def test_equal_rates_reduce_to_bgk_with_guo_forcing():
+    """With every relaxation rate equal (s = 1/tau), sigma = 0 and no Q term
+    the MRT collision with the forcing source S of Eq. S is the BGK
+    collision with Guo's forcing term, written here in population space:
+    f* = f - (f - f_eq(rho, u)) / tau + (1 - 1/(2 tau)) F_i with
+    F_i = w_i [3 (c_i - u).F + 9 (c_i.u)(c_i.F)] and u = (j + F/2)/rho.
+    This pins every force term of S (the u.F parts of e and epsilon and the
+    stress sources 2(u_x F_x - u_y F_y), u_x F_y + u_y F_x), the
+    equilibrium moments and M, M^-1 against the textbook scheme."""
+    rng = np.random.default_rng(21)
+    cx = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], dtype=float)
+    cy = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], dtype=float)
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    for tau in (0.6, 0.83, 1.7):
+        ny, nx = 3, 4
+        p = Params(nx=nx, ny=ny, a=A, sigma=0.0, kappa=0.0, s_rho=1 / tau, s_e=1 / tau,
+                   s_zeta=1 / tau, s_j=1 / tau, s_q=1 / tau, eta_l=(tau - 0.5) / 3,
+                   eta_v=(tau - 0.5) / 3, rho_l=RL, rho_v=RV)
+        s = Sim(p)
+        f = rng.uniform(0.05, 0.7, (9, ny, nx))
+        rho = f.sum(0)
+        jx, jy = np.tensordot(cx, f, 1), np.tensordot(cy, f, 1)
+        fx, fy = rng.uniform(-0.02, 0.02, (2, ny, nx))
+        ux, uy = (jx + 0.5 * fx) / rho, (jy + 0.5 * fy) / rho
+        z = np.zeros_like(rho)
+        got = s.collide(f, rho, ux, uy, fx, fy, fx, fy, np.ones_like(rho), z, z, z)
+        u2 = ux * ux + uy * uy
+        for i in range(9):
+            cu = cx[i] * ux + cy[i] * uy
+            feq = w[i] * rho * (1 + 3 * cu + 4.5 * cu * cu - 1.5 * u2)
+            fi = w[i] * (3 * ((cx[i] - ux) * fx + (cy[i] - uy) * fy) + 9 * cu * (cx[i] * fx + cy[i] * fy))
+            want = f[i] - (f[i] - feq) / tau + (1 - 0.5 / tau) * fi
+            np.testing.assert_allclose(got[i], want, rtol=0, atol=1e-14)
+
+
+def test_sigma_and_kappa_terms_shift_the_e_and_epsilon_equilibria():
+    """Structure of the sigma term of S and of C (Eqs. S, C): written as
+    sources they are rate-independent shifts of the equilibria of the
+    energy moments, equal and opposite for e and epsilon (X = 12 sigma
+    |F^m|^2 / psi^2 + 3/2 (Q_xx + Q_yy)), i.e. an isotropic pressure change
+    that moves mass only between the rest and the moving populations.
+    Collisions repeated on one node with its macroscopic state held fixed
+    (at rest, so that the u.F part of S, whose shift does depend on the
+    rate, vanishes) converge to the same e and epsilon for any rates s_e,
+    s_zeta, with e - e_eq = -(eps - eps_eq) = X.  (These two moments are
+    not hydrodynamic; the planar and Laplace pins see only the e part.)"""
+    cx = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], dtype=float)
+    cy = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], dtype=float)
+    c2 = cx * cx + cy * cy
+    be, beps = -4 + 3 * c2, 4 - 10.5 * c2 + 4.5 * c2 * c2
+    one = np.ones((1, 1))
+    rho, ux, uy = 2.1 * one, 0.0 * one, 0.0 * one
+    fmx, fmy, psi = 0.011 * one, -0.017 * one, 1.7 * one
+    qxx, qyy, qxy = 0.004 * one, -0.0015 * one, 0.002 * one
+    sigma = 0.11
+    u2 = ux * ux + uy * uy
+    e_eq, eps_eq = rho * (-2 + 3 * u2), rho * (1 - 3 * u2)
+    X = 12 * sigma * (fmx ** 2 + fmy ** 2) / psi ** 2 + 1.5 * (qxx + qyy)
+    fixed = []
+    for se, sz in ((0.8, 1.3), (1.25, 1.25), (1.6, 0.7)):
+        p = Params(nx=1, ny=1, a=A, sigma=sigma, kappa=0.3, s_e=se, s_zeta=sz, rho_l=RL, rho_v=RV)
+        s = Sim(p)
+        f = feq_weights(rho, ux, uy)
+        for _ in range(200):
+            f = s.collide(f, rho, ux, uy, fmx, fmy, fmx, fmy, psi, qxx, qyy, qxy)
+        e = float((be[:, None, None] * f).sum())
+        eps = float((beps[:, None, None] * f).sum())
+        fixed.append((e, eps))
+        assert abs((e - e_eq[0, 0]) - X[0, 0]) < 1e-13, (se, sz)
+        assert abs((eps - eps_eq[0, 0]) + X[0, 0]) < 1e-13, (se, sz)
+    fixed = np.asarray(fixed)
+    assert np.abs(fixed - fixed[0]).max() < 1e-13
+
+
+def test_gravity_pulls_the_liquid_down_and_conserves_total_momentum():
+    """Eq. gravitational_force with rho_bar the mean density: on a periodic
+    lattice the body forces sum to zero (total momentum is conserved to
+    rounding), and a liquid slab between vapour layers gains momentum along
+    g at the rate g sum_liquid (rho - rho_bar) (its two interfaces pull
+    equally in opposite directions): after five steps within 3 % of that."""
+    ny, nx = 80, 2
+    y = np.arange(ny)[:, None].astype(float) * np.ones((1, nx))
+    rho = wl.tanh_blend(np.abs(y - ny / 2), 15, 0.5, RL, RV)
+    g = -2e-5
+    s = Sim(Params(nx=nx, ny=ny, a=A, sigma=0.1, kappa=0.1, rho_l=RL, rho_v=RV, gy=g))
+    s.init_fields(rho, T=np.full_like(rho, T86))
+    liq = rho > 0.5 * (RL + RV)
+    gain = g * (rho[liq] - rho.mean()).sum()
+    s.step(5)
+    jy = np.tensordot(lat.CY.astype(float), s.populations(), 1)
+    assert abs(jy.sum()) < 1e-9 * abs(gain)
+    assert abs(jy[liq].sum() / (5 * gain) - 1) < 0.03, jy[liq].sum() / (5 * gain)
+
+
 def test_wall_closure_gives_zero_fluid_velocity():
     """After the Zou-He closure the wall nodes carry momentum -F^m/2, so the
     fluid velocity (j + F/2)/rho is only the buoyancy part; the closed
@@ -248,6 +342,26 @@ def test_planar_coexistence_matches_sigma_theory(case):
     r = s.fields()[0][:, 0]
     assert abs(r[0] / rv - 1) < 6e-3
     assert abs(r[ny // 2] / rl - 1) < 1.5e-2
+
+
+def test_planar_interface_does_not_see_kappa():
+    """The kappa correction adds (3/4) tr(Q) I - Q to the pressure tensor
+    (reading R13), zero in the normal direction of a flat interface, so the
+    coexistence profile of a planar slab does not depend on kappa.  With
+    equal relaxation rates (the droplet rates of Sec. 4.1) this holds on
+    the lattice to rounding; a C term for e scaled by 2/3 moves the
+    profile by 4e-2."""
+    ny = 64
+    y = np.arange(ny)[:, None].astype(float)
+    rho = wl.tanh_blend(np.abs(y - ny / 2), 16, 0.5, RL, RV)
+    prof = {}
+    for k in (0.0, 0.3, -0.2):
+        s = Sim(Params(nx=1, ny=ny, a=A, sigma=0.1, kappa=k, rho_l=RL, rho_v=RV))
+        s.init_fields(rho, T=np.full_like(rho, T86))
+        s.step(3000)
+        prof[k] = s.fields()[0][:, 0]
+    for k in (0.3, -0.2):
+        assert np.abs(prof[k] - prof[0.0]).max() < 1e-10, k
 
 
 def test_dirichlet_conduction_reaches_linear_profile():
