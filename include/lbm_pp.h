@@ -95,7 +95,9 @@ typedef struct lbm_params {
                                     LBM_WALL_MODIFIED_PSI: adhesion of Eq. mod-psi-based-formula
                                     with per-column strengths G_w, Q of Eq. Q-mod-psi-based.
                                     Either way the Zou-He closure imposes zero fluid velocity
-                                    with the chosen F^m (wall density from a Newton solve) */
+                                    with the chosen F^m and the buoyancy F^b taken with the
+                                    mean density whose wall nodes are at their known parts
+                                    (wall density from a Newton solve) */
   int32_t outflow_top;           /* 1: row ny-1 is a zero-gradient outflow (the open end of the
                                     1-D boiling problem, Sec. 4.2) instead of a wall: its
                                     populations entering from above are those of row ny-2, psi

@@ -32,12 +32,14 @@ Step n -> n+1 (Sec. 2), in this order:
      by the Zou-He closure at the start of the next step (step 1').
   1'. wall nodes (Zou-He, wet node): the known populations give
      K = f0 + f1 + f3 + 2 (f4 + f7 + f8) (bottom; mirror image at the top);
-     the closure prescribes the momentum j_w = -F^m/2, i.e. zero fluid
-     velocity u = (j + F/2)/rho up to the tiny buoyancy part; its normal
-     component makes the wall density solve rho -/+ F^m_y(rho)/2 = K, a
-     scalar equation per node (F^m_y depends on the node's own psi and on
-     the adjacent interior row only) solved by NEWTON_WALL Newton steps
-     from rho = K; the tangential component only splits the unknowns.
+     the closure prescribes the momentum j_w = -F/2 with F = F^m + F^b
+     (R4), i.e. zero fluid velocity u = (j + F/2)/rho up to a remainder of
+     order |g| |F^m| / ny; its normal component makes the wall density
+     solve rho + F_y(rho)/2 = K at the bottom and rho - F_y(rho)/2 = K at
+     the top, F_y = F^m_y(rho) + g (rho - rho_bar_K), a scalar equation per
+     node (F^m_y depends on the node's own psi and on the adjacent interior
+     row only) solved by NEWTON_WALL Newton steps from rho = K; the
+     tangential component only splits the unknowns.
      With outflow_top the top row is no wall but a zero-gradient outflow
      (the 1-D boiling problem of Sec. 4.2): after streaming (and at init)
      its populations with c_y < 0 are copied from the row below, psi above
@@ -54,11 +56,15 @@ the GPU library):
   R4 no-slip at a wet node means zero fluid velocity, and the fluid
      velocity of this forcing scheme is u = (sum f c + F/2)/rho
      (Eq. DensityAndVelocityRelationToF), so the Zou-He closure imposes
-     sum f c = -F^m/2 (F^m including F^ads).  Imposing sum f c = 0 instead
-     injects or removes about 3 F_y/4 of mass per wall node and step at
-     wetting walls and makes the heated pool unstable.  F^b is left out of
-     the closure so that the closure stays local (F^b needs the global
-     rho_bar); this leaves a wall velocity F^b/(2 rho), of order |g|;
+     sum f c = -F/2 with F = F^m + F^b (F^m including F^ads).  Imposing
+     sum f c = 0 instead injects or removes about 3 F_y/4 of mass per wall
+     node and step at wetting walls and makes the heated pool unstable.
+     The closure's F^b = g (rho - rho_bar_K) takes rho_bar_K, the mean
+     density with every wall node counted at its known part K, because the
+     closed wall densities cannot enter the buoyancy they balance; the
+     wall velocity left is g (rho_bar_K - rho_bar) / (2 rho), of order
+     |g| |F^m| / ny (without F^b the closure left F^b/(2 rho), of order
+     |g|, and the pool lost mass through both walls);
   R5 rho_bar is the mean of rho^n over every node, before the forces;
   R6 finite differences: grad phi = sum_i W_i phi(x + c_i) c_i and
      lap phi = 6 sum_i w_i (phi(x + c_i) - phi(x)) (isotropic D2Q9), and
@@ -78,9 +84,12 @@ Domain errors (rho <= 0, rho >= 1/b, psi radicand <= 0, T <= 0, NaN) raise
 DomainError: the method is undefined there; nothing is clamped.
 
 Parity pins: tests/test_oracle_step.py (conservation invariants, uniform
-fixed point, MRT shear-wave viscosity, RK2 Fourier amplification, stencil
-exactness, Zou-He momentum, mass conservation, planar coexistence vs.
-Maxwell and the sigma fit, Laplace law).
+fixed point, MRT shear-wave viscosity, equal-rate reduction to BGK with
+Guo forcing, the energy-moment shifts of the sigma and kappa terms,
+buoyancy momentum balance, RK2 Fourier amplification, stencil exactness,
+Zou-He momentum, mass conservation (periodic, and at walls under
+gravity), planar coexistence vs. Maxwell, the sigma fit and kappa,
+Laplace law).
 """
 from dataclasses import dataclass, field
 
@@ -383,11 +392,35 @@ class Sim:
         return f
 
     # ------------------------------------------------------------- full step
-    def wall_closure(self, f, T):
-        """Step 1': returns (f closed, rho_bottom, rho_top) for the two wall
-        rows; f is copied, the unknown populations are rebuilt later by
-        close_populations once F^m at the wall nodes is known."""
+    def known_parts(self, f):
+        """Known part K of the density of each wall row (bottom, top; None
+        for an outflow top): K = f0 + f1 + f3 + 2 (f4 + f7 + f8) at the
+        bottom, its mirror image at the top."""
+        ny = self.p.ny
+        b = f[:, 0, :]
+        kb = b[0] + b[1] + b[3] + 2.0 * (b[4] + b[7] + b[8])
+        if self.p.outflow_top:
+            return kb, None
+        t = f[:, ny - 1, :]
+        return kb, t[0] + t[1] + t[3] + 2.0 * (t[2] + t[5] + t[6])
+
+    def mean_known_density(self, f):
+        """rho_bar_K of the closure (R4): the mean density with each wall
+        node counted at its known part K (the closure's own result cannot
+        enter the buoyancy it balances)."""
+        ny = self.p.ny
+        kb, kt = self.known_parts(f)
+        top = f[:, ny - 1, :].sum(axis=0) if kt is None else kt
+        tot = kb.sum() + f[:, 1:ny - 1, :].sum() + top.sum()
+        return tot / (self.p.nx * ny)
+
+    def wall_closure(self, f, T, rho_bar_k=0.0):
+        """Step 1': returns (rho_bottom, rho_top) of the two wall rows; the
+        unknown populations are rebuilt later by close_populations once F^m
+        at the wall nodes is known.  The prescribed momentum is -F/2 with
+        F = F^m + F^b, F^b = g (rho - rho_bar_k) (R4)."""
         p, eos, G, ny = self.p, self.eos, self.p.G, self.p.ny
+        gy = p.gy
         rho_int = f[:, 1:ny - 1, :].sum(axis=0)
         psi_int = eos.psi(rho_int, T[1:ny - 1, :])
         out = []
@@ -395,36 +428,35 @@ class Sim:
         if p.outflow_top:
             rows = rows[:1]
             out = [None]  # no closure at the top: its density is the plain sum
+        kb, kt = self.known_parts(f)
         for row, adj, sgn, rw in rows:
-            fr = f[:, row, :]
-            if sgn > 0:
-                K = fr[0] + fr[1] + fr[3] + 2.0 * (fr[4] + fr[7] + fr[8])
-            else:
-                K = fr[0] + fr[1] + fr[3] + 2.0 * (fr[2] + fr[5] + fr[6])
+            K = kb if sgn > 0 else kt
             pa = psi_int[adj - 1]
             # F^m_y: fluid neighbours in the adjacent row (weights 1/3,
             # 1/12, 1/12, c_y = sgn), solid ones (c_y = -sgn, weights summing
             # to 1/2)
             nbsum = pa / 3.0 + (np.roll(pa, -1) + np.roll(pa, 1)) / 12.0
             r = K.copy()
+            # the normal component: bottom rho + F_y / 2 = K, top
+            # rho - F_y / 2 = K, with F_y = F^m_y(rho) + g (rho - rho_bar_k)
             if p.wall_model == PSI_BASED:
-                # F^m_y = psi(rho) B with psi_w for the solid neighbours;
-                # bottom: rho + psi(rho) B / 2 = K ; top: rho - psi(rho) B / 2 = K
+                # F^m_y = psi(rho) B with psi_w for the solid neighbours
                 pw = eos.psi(rw, T[row])
                 B = -G * sgn * (nbsum - 0.5 * pw)
                 for _ in range(NEWTON_WALL):
-                    g = r + sgn * 0.5 * eos.psi(r, T[row]) * B - K
-                    dg = 1.0 + sgn * 0.5 * eos.dpsi_drho(r, T[row]) * B
+                    g = r + sgn * 0.5 * (eos.psi(r, T[row]) * B + gy * (r - rho_bar_k)) - K
+                    dg = 1.0 + sgn * 0.5 * (eos.dpsi_drho(r, T[row]) * B + gy)
                     r = r - g / dg
             else:
                 # Eq. mod-psi-based-formula: F^m_y = sgn (-G psi nbsum +
-                # G_w psi^2 / 2), so rho + (-G psi nbsum + G_w psi^2 / 2) / 2 = K
+                # G_w psi^2 / 2)
                 gw = p.gw_bottom if sgn > 0 else p.gw_top
                 for _ in range(NEWTON_WALL):
                     ps = eos.psi(r, T[row])
                     dps = eos.dpsi_drho(r, T[row])
-                    g = r + 0.5 * (-G * ps * nbsum + 0.5 * gw * ps * ps) - K
-                    dg = 1.0 + 0.5 * (-G * nbsum + gw * ps) * dps
+                    g = (r + 0.5 * (-G * ps * nbsum + 0.5 * gw * ps * ps)
+                         + sgn * 0.5 * gy * (r - rho_bar_k) - K)
+                    dg = 1.0 + 0.5 * (-G * nbsum + gw * ps) * dps + sgn * 0.5 * gy
                     r = r - g / dg
             out.append(r)
         return (out[1], out[0]) if p.outflow_top else (out[0], out[1])
@@ -453,8 +485,11 @@ class Sim:
         p = self.p
         f = f.copy()
         rho, jx, jy = self.moments(f)
+        rho_bar_k = 0.0
         if p.walls:
-            rb, rt = self.wall_closure(f, T)
+            if p.gy != 0.0:
+                rho_bar_k = self.mean_known_density(f)
+            rb, rt = self.wall_closure(f, T, rho_bar_k)
             rho[0, :] = rb
             if not p.outflow_top:
                 rho[p.ny - 1, :] = rt
@@ -470,11 +505,13 @@ class Sim:
         if p.walls:
             ny = p.ny
             top = f[:, ny - 1].copy()
-            self.close_populations(f, -0.5 * fmx[0], -0.5 * fmy[0],
-                                   -0.5 * fmx[ny - 1], -0.5 * fmy[ny - 1])
-            for row in ((0,) if p.outflow_top else (0, ny - 1)):
+            # prescribed wall momentum -(F^m + F^b)/2, F^b with rho_bar_k (R4)
+            fby = [p.gy * (rho[row] - rho_bar_k) for row in (0, ny - 1)]
+            self.close_populations(f, -0.5 * fmx[0], -0.5 * (fmy[0] + fby[0]),
+                                   -0.5 * fmx[ny - 1], -0.5 * (fmy[ny - 1] + fby[1]))
+            for row, fb in (((0, fby[0]),) if p.outflow_top else ((0, fby[0]), (ny - 1, fby[1]))):
                 jx[row] = -0.5 * fmx[row]
-                jy[row] = -0.5 * fmy[row]
+                jy[row] = -0.5 * (fmy[row] + fb)
             if p.outflow_top:
                 f[:, ny - 1] = top
         ux = (jx + 0.5 * fx) / rho

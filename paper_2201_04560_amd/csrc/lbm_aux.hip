@@ -103,6 +103,15 @@ __device__ __forceinline__ void wall_mass_body(const WallArgs<S>& A, const int b
   const int id = bid * blockDim.x + threadIdx.x;
   double dm = 0.0;
   uint32_t err = 0;
+  // rho_bar_k of the closure's buoyancy: the step kernel's sum of the
+  // known-part partials, in the same order (every lane of the wave takes
+  // part, before the lanes split)
+  const double* part = A.part_in;
+  const double rbk =
+      A.ph.gy != 0.0
+          ? fixed_order_sum([&](int i) { return part[i]; }, A.npart_in, int(threadIdx.x & (kLanes - 1))) /
+                (double(A.nx) * double(A.ny))
+          : 0.0;
   if (id < 2 * A.nx) {
     const bool bot = id < A.nx;
     const int x = bot ? id : id - A.nx;
@@ -139,11 +148,11 @@ __device__ __forceinline__ void wall_mass_body(const WallArgs<S>& A, const int b
     const double rw = bot ? A.tab.rho_w_b[x] : A.tab.rho_w_t[x];  // rho_w, or G_w (modified-psi)
     if (A.ph.wall_mod) {
       const double nbsum = pa[0] / 3.0 + (pa[1] + pa[2]) / 12.0;
-      dm = wall_density_mod(K, nbsum, rw, Tw, A.ph) - K;
+      dm = wall_density_mod(K, nbsum, rw, Tw, sgn, A.ph, rbk) - K;
     } else {
       const double psiw = psi_checked(rw, Tw, A.ph, err);
       const double B = wall_coef_B(pa[0], pa[1], pa[2], psiw, sgn, A.ph);
-      dm = wall_density(K, B, Tw, sgn, A.ph) - K;
+      dm = wall_density(K, B, Tw, sgn, A.ph, rbk) - K;
     }
   }
   __shared__ double red[256 / kLanes];
@@ -263,11 +272,11 @@ hipError_t launch_wall_mass(const LaunchWall& L, hipStream_t st) {
   const dim3 grid(wall_blocks(L.nx)), block(256);
   if (L.fp32) {
     WallArgs<float> a{static_cast<const float*>(L.fin), static_cast<const float*>(L.Tin), L.wall_out,
-                      L.tab, L.ph, L.nx, L.ny, L.pitch, L.plane};
+                      L.part_in, L.npart_in, L.tab, L.ph, L.nx, L.ny, L.pitch, L.plane};
     hipLaunchKernelGGL((lbm_wall_mass_kernel<float, float>), grid, block, 0, st, a);
   } else {
     WallArgs<double> a{static_cast<const double*>(L.fin), static_cast<const double*>(L.Tin), L.wall_out,
-                       L.tab, L.ph, L.nx, L.ny, L.pitch, L.plane};
+                       L.part_in, L.npart_in, L.tab, L.ph, L.nx, L.ny, L.pitch, L.plane};
     hipLaunchKernelGGL((lbm_wall_mass_kernel<double, double>), grid, block, 0, st, a);
   }
   return hipGetLastError();
@@ -283,11 +292,11 @@ size_t wall_desc_bytes(int fp32) { return fp32 ? sizeof(WallArgs<float>) : sizeo
 void fill_wall_desc(const LaunchWall& L, void* out) {
   if (L.fp32) {
     WallArgs<float> a{static_cast<const float*>(L.fin), static_cast<const float*>(L.Tin), L.wall_out,
-                      L.tab, L.ph, L.nx, L.ny, L.pitch, L.plane};
+                      L.part_in, L.npart_in, L.tab, L.ph, L.nx, L.ny, L.pitch, L.plane};
     std::memcpy(out, &a, sizeof a);
   } else {
     WallArgs<double> a{static_cast<const double*>(L.fin), static_cast<const double*>(L.Tin), L.wall_out,
-                       L.tab, L.ph, L.nx, L.ny, L.pitch, L.plane};
+                       L.part_in, L.npart_in, L.tab, L.ph, L.nx, L.ny, L.pitch, L.plane};
     std::memcpy(out, &a, sizeof a);
   }
 }

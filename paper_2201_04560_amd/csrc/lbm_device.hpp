@@ -169,9 +169,11 @@ __device__ __forceinline__ double psi_fast(double rho, double T, const EosNode& 
 }
 
 // ----------------------------------------------------------- wall closure
-// Zou-He at a wet wall node with prescribed momentum -F^m/2: the wall
-// density solves rho + sgn psi(rho) B / 2 = K (sgn = +1 bottom, -1 top),
-// where F^m_y = psi(rho) B.  Fixed number of Newton steps from rho = K.
+// Zou-He at a wet wall node with prescribed momentum -F/2, F = F^m + F^b:
+// the wall density solves rho + sgn (psi(rho) B + gy (rho - rbk)) / 2 = K
+// (sgn = +1 bottom, -1 top), where F^m_y = psi(rho) B and the buoyancy
+// F^b_y = gy (rho - rbk) takes rbk, the mean density with every wall node
+// counted at its known part K.  Fixed number of Newton steps from rho = K.
 __device__ __forceinline__ double wall_coef_B(double nb_c, double nb_p, double nb_m, double psi_w,
                                               double sgn, const Phys& p) {
   const double nbsum = nb_c / 3.0 + (nb_p + nb_m) / 12.0;
@@ -179,13 +181,13 @@ __device__ __forceinline__ double wall_coef_B(double nb_c, double nb_p, double n
 }
 
 __device__ __forceinline__ double wall_density(double K, double B, double T, double sgn,
-                                               const Phys& p) {
+                                               const Phys& p, double rbk) {
   double r = K;
 #pragma unroll 1
   for (int it = 0; it < kNewtonWall; ++it) {
     const double ps = sqrt(psi_radicand(r, T, p));
-    const double g = r + sgn * 0.5 * ps * B - K;
-    const double dg = 1.0 + sgn * 0.5 * dpsi_drho(r, T, ps, p) * B;
+    const double g = r + sgn * 0.5 * (ps * B + p.gy * (r - rbk)) - K;
+    const double dg = 1.0 + sgn * 0.5 * (dpsi_drho(r, T, ps, p) * B + p.gy);
     r = r - g / dg;
   }
   return r;
@@ -196,14 +198,14 @@ __device__ __forceinline__ double wall_density(double K, double B, double T, dou
 // fluid velocity asks rho + (-G psi nbsum + G_w psi^2 / 2) / 2 = K at both
 // walls; Newton from rho = K
 __device__ __forceinline__ double wall_density_mod(double K, double nbsum, double gw, double T,
-                                                   const Phys& p) {
+                                                   double sgn, const Phys& p, double rbk) {
   double r = K;
 #pragma unroll 1
   for (int it = 0; it < kNewtonWall; ++it) {
     const double ps = sqrt(psi_radicand(r, T, p));
     const double dps = dpsi_drho(r, T, ps, p);
-    const double g = r + 0.5 * (-p.G * ps * nbsum + 0.5 * gw * ps * ps) - K;
-    const double dg = 1.0 + 0.5 * (-p.G * nbsum + gw * ps) * dps;
+    const double g = r + 0.5 * (-p.G * ps * nbsum + 0.5 * gw * ps * ps) + sgn * 0.5 * p.gy * (r - rbk) - K;
+    const double dg = 1.0 + 0.5 * (-p.G * nbsum + gw * ps) * dps + sgn * 0.5 * p.gy;
     r = r - g / dg;
   }
   return r;
@@ -225,6 +227,22 @@ __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kLanes);
   return v;
+}
+
+// Sum of n values in one fixed order, the same in every caller: lane l
+// adds entries l, l + 64, ... into eight interleaved accumulators (eight
+// loads in flight), then the accumulators and the lanes combine.  ld(i)
+// loads entry i.
+template <class LD>
+__device__ __forceinline__ double fixed_order_sum(LD ld, int n, int lane) {
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int i = lane;
+  for (; i + 7 * kLanes < n; i += 8 * kLanes) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] += ld(i + k * kLanes);
+  }
+  for (; i < n; i += kLanes) a[0] += ld(i);  // fewer than 8 left per lane
+  return wave_sum(((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7])));
 }
 
 __device__ __forceinline__ double wave_max(double v) {

@@ -85,6 +85,8 @@ struct WallArgs {
   const S* fin;
   const S* Tin;
   double* wall_out;
+  const double* part_in;  // known-part density partials of the step (rho_bar_k)
+  int npart_in;
   Tables tab;
   Phys ph;
   int nx, ny, pitch;
@@ -96,6 +98,8 @@ struct LaunchWall {
   const void* fin;
   const void* Tin;
   double* wall_out;
+  const double* part_in;
+  int npart_in;
   Tables tab;
   Phys ph;
   int nx, ny, pitch;

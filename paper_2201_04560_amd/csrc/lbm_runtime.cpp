@@ -463,6 +463,8 @@ LaunchWall lbm::wall_args(lbm_ctx* c, const LaunchStep& L) {
   W.fin = L.fin;
   W.Tin = L.Tin;
   W.wall_out = c->wall();
+  W.part_in = L.part_in;
+  W.npart_in = L.npart_in;
   W.tab = L.tab;
   W.ph = c->ph;
   W.nx = c->p.nx;

@@ -133,20 +133,6 @@ __device__ __forceinline__ void bstore(rsrc_t r, uint32_t voff, uint32_t soff, d
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
 }
 
-template <bool GA>
-__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int npart,
-                                               const double* __restrict__ wall, int nwall, int lane) {
-  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  int i = lane;
-  for (; i + 7 * kLanes < npart; i += 8 * kLanes) {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) a[k] += gld<GA>(part + i + k * kLanes);
-  }
-  for (; i < npart; i += kLanes) a[0] += gld<GA>(part + i);  // fewer than 8 left per lane
-  for (int j = lane; j < nwall; j += kLanes) a[1] += gld<GA>(wall + j);
-  const double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
-  return wave_sum(s);
-}
 
 // isotropic D2Q9 stencils on a 3x3 neighbourhood [dy+1][dx+1]:
 //   grad f = sum W_i f(x + c_i) c_i,  lap f = 6 sum w_i (f(x + c_i) - f(x))
@@ -348,11 +334,20 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
   __shared__ C s_ir[WS ? R : 1][kLanes];
   constexpr int kColl = 21;  // collision inputs of a node
 
-  // mean density of the current state (Eq. gravitational_force): the
-  // partials are summed in the same order by every workgroup
-  double rho_bar = 0.0;
-  if (P.gy != 0.0) rho_bar = sum_partials<GA>(A.part_in, A.npart_in, A.wall_in, A.nwall_in, lane) /
-                             (double(nx) * double(ny));
+  // mean density of the current state (Eq. gravitational_force), and for
+  // the wall closure the mean with every wall node at its known part: the
+  // partials (known-part densities of every node) and the closure's
+  // corrections are summed in the same order by every workgroup
+  double rho_bar = 0.0, rho_bar_k = 0.0;
+  if (P.gy != 0.0) {
+    const double* part = A.part_in;
+    const double* wall = A.wall_in;
+    const double sp = fixed_order_sum([&](int i) { return gld<GA>(part + i); }, A.npart_in, lane);
+    const double sw = fixed_order_sum([&](int i) { return gld<GA>(wall + i); }, A.nwall_in, lane);
+    const double n = double(nx) * double(ny);
+    rho_bar_k = sp / n;
+    rho_bar = (sp + sw) / n;
+  }
 
   // issue the loads of row r into (gn, Tn)
   auto load_row = [&](int r, C (&gn)[9], C& Tn) {
@@ -572,14 +567,14 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
     double psiw, rwall, psiwall;
     if (wall_mod) {
       const double nbsum = s_psi[SN][lane] / 3.0 + (s_psi[SN][lp] + s_psi[SN][lm]) / 12.0;
-      rwall = wall_density_mod(K, nbsum, rw, Tw, P);
+      rwall = wall_density_mod(K, nbsum, rw, Tw, sgn, P, rho_bar_k);
       psiwall = psi_checked(rwall, Tw, P, err);
       // solid neighbours seen by F^m: G psi psi_s = G_w psi^2
       psiw = rw / P.G * psiwall;
     } else {
       psiw = psi_checked(rw, Tw, P, err);
       const double B = wall_coef_B(s_psi[SN][lane], s_psi[SN][lp], s_psi[SN][lm], psiw, sgn, P);
-      rwall = wall_density(K, B, Tw, sgn, P);
+      rwall = wall_density(K, B, Tw, sgn, P, rho_bar_k);
       psiwall = psi_checked(rwall, Tw, P, err);
     }
     s_rho[SW][lane] = rwall;
@@ -763,9 +758,10 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
     const double qxy = kq2 * ((1.0 / 12.0) * ((d5 + d7) - (d6 + d8)));
 
     if (wb || wt) {
-      // Zou-He reconstruction for the prescribed momentum -F^m/2
+      // Zou-He reconstruction for the prescribed momentum -(F^m + F^b)/2,
+      // the closure's buoyancy taken with rho_bar_k
       jxs = C(-0.5 * fmx);
-      jys = C(-0.5 * fmy);
+      jys = C(-0.5 * (fmy + P.gy * (rho - rho_bar_k)));
       const C d = C(0.5) * (gp[1] - gp[3]);
       if (wb) {
         gp[2] = gp[4] + C(2.0 / 3.0) * jys;
