@@ -677,3 +677,30 @@ def test_gravity_momentum_balance():
           flush=True)
     assert abs(jy.sum()) < 1e-9 * abs(gain)
     assert abs(jy[liq].sum() / (5 * gain) - 1) < 0.03
+
+
+def test_gravity_adds_no_mass_leak_at_walls():
+    """Reading R4 on the GPU (float64): a liquid layer under vapour between
+    two wetting Zou-He walls keeps its mass with gravity as it does without
+    (the wet-node closure's own settling oscillation aside): after 8000
+    steps the two mass histories end within 2e-4 of each other (a closure
+    without the buoyancy loses about 1e-3 here)."""
+    print("case walls gravity mass", flush=True)
+    import workloads as wl
+
+    nx, ny = 64, 120
+    eos, T, rv, rl = cases.coexistence()
+    y = np.arange(ny)[:, None].astype(float) * np.ones((1, nx))
+    rho = wl.tanh_blend(y, 60, 0.5, rl, rv)
+    drift = []
+    for gy in (0.0, -2e-5):
+        c = dict(nx=nx, ny=ny, a=2.0 / 49.0, sigma=0.1, kappa=0.1, rho_l=rl, rho_v=rv, gy=gy,
+                 walls=True, rho_w_bottom=rl, rho_w_top=rv, **wl.POOL_RATES)
+        lat = _lat(c)
+        lat.init_fields(rho, None, None, np.full_like(rho, T))
+        m0 = lat.norms()["mass"]
+        lat.step(8000)
+        drift.append(lat.norms()["mass"] / m0 - 1)
+        lat.close()
+    print(f"mass drift g=0 {drift[0]:.2e}, g=-2e-5 {drift[1]:.2e}", flush=True)
+    assert abs(drift[1] - drift[0]) < 2e-4, drift
