@@ -103,15 +103,33 @@ __device__ __forceinline__ void wall_mass_body(const WallArgs<S>& A, const int b
   const int id = bid * blockDim.x + threadIdx.x;
   double dm = 0.0;
   uint32_t err = 0;
-  // rho_bar_k of the closure's buoyancy: the step kernel's sum of the
-  // known-part partials, in the same order (every lane of the wave takes
-  // part, before the lanes split)
-  const double* part = A.part_in;
-  const double rbk =
-      A.ph.gy != 0.0
-          ? fixed_order_sum([&](int i) { return part[i]; }, A.npart_in, int(threadIdx.x & (kLanes - 1))) /
-                (double(A.nx) * double(A.ny))
-          : 0.0;
+  // rho_bar_k of the closure's buoyancy: the step kernel's fixed-order sum
+  // of the known-part partials (fixed_order_sum), its eight accumulators
+  // spread over the block's four waves (two each, all loads in flight at
+  // once) and combined in the same order, so the result is the step
+  // kernel's bit for bit (every thread takes part, before the lanes split)
+  __shared__ double s_acc[8][kLanes];
+  double rbk = 0.0;
+  if (A.ph.gy != 0.0) {
+    static_assert(256 / kLanes * 2 == 8, "four waves of two accumulators");
+    const double* part = A.part_in;
+    const int n = A.npart_in;
+    const int w = int(threadIdx.x / kLanes), l = int(threadIdx.x & (kLanes - 1));
+    double a0 = 0.0, a1 = 0.0;
+    int i = l;
+    for (; i + 7 * kLanes < n; i += 8 * kLanes) {
+      a0 += part[i + 2 * w * kLanes];
+      a1 += part[i + (2 * w + 1) * kLanes];
+    }
+    if (w == 0)
+      for (; i < n; i += kLanes) a0 += part[i];  // fewer than 8 left per lane
+    s_acc[2 * w][l] = a0;
+    s_acc[2 * w + 1][l] = a1;
+    __syncthreads();
+    const double t = ((s_acc[0][l] + s_acc[1][l]) + (s_acc[2][l] + s_acc[3][l])) +
+                     ((s_acc[4][l] + s_acc[5][l]) + (s_acc[6][l] + s_acc[7][l]));
+    rbk = wave_sum(t) / (double(A.nx) * double(A.ny));
+  }
   if (id < 2 * A.nx) {
     const bool bot = id < A.nx;
     const int x = bot ? id : id - A.nx;
