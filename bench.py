@@ -821,8 +821,9 @@ def main():
                     help="also run the Sec. 4.2 1-D boiling refinement (columns of 160..2560 "
                          "nodes, both parameter sets, 40000 base steps, float64, about 4 min "
                          "of GPU time)")
-    ap.add_argument("--pool-steps", type=int, default=5000,
-                    help="steps of the 1024 x 2048 pool in the float32 accuracy check")
+    ap.add_argument("--pool-steps", type=int, default=50000,
+                    help="steps of the 1024 x 2048 pool in the float32 accuracy check (the "
+                         "configuration's 50,000 by default, about 10 s of GPU time)")
     ap.add_argument("--tile-cache", default=None, help="JSON cache of autotuned strip heights")
     ap.add_argument("--no-autotune", action="store_true",
                     help="library default strip heights instead of the autotuner")
