@@ -926,8 +926,8 @@ def main():
                                "sigma=kappa=0.1, cv=6, lambda=2/3, no gravity; a step advances the "
                                "four seeds by one time step",
                    "nx": nx, "ny": ny, "lattices": len(SEEDS),
-                   "storage": "f32 shifted populations (f - w rho_v) + f32 T; f64 EOS/psi/forces "
-                              "and reductions" if main_name == "fp32" else "f64",
+                   "storage": "f32 shifted populations (f - w rho_v) + f32 T; f64 EOS/psi, wall "
+                              "closure and reductions" if main_name == "fp32" else "f64",
                    "launch": ("one batched multi-lattice launch per step, " +
                               ("graph-replayed" if m.get("use_graph") else "launched directly") +
                               (" (the faster of the two over 200 steps)" if args.launch == "auto" else ""))

@@ -27,8 +27,13 @@
 // with the modified-psi model or the zero-gradient outflow top.
 //
 // Storage S is double (plain step) or float (populations stored as
-// g_i = f_i - w_i rho_ref).  C is the type of the collision and energy
-// arithmetic.  EOS, psi, forces and Q are float64 in both.
+// g_i = f_i - w_i rho_ref).  C is the type of the collision, energy,
+// force and Q arithmetic.  The EOS and psi (and the wall closure's Newton
+// solve) are float64 in both: psi near the spinodal needs its digits,
+// while the forces and Q, weighted sums of psi differences between
+// neighbours, feed the float32 collision (on the 4 x 512^2 vaporisation:
+// step 25.7 -> 25.3 us, density deviation from float64 after 20,000 steps
+// 1.21e-3 -> 1.22e-3, against float64 forces and Q, MI355X).
 #include <cstring>
 #include <type_traits>
 
@@ -319,7 +324,7 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
   // rings of R rows indexed by (row - first row) & (R - 1)
   constexpr int R = WS ? 8 : 4 * RPI;  // ring rows
   __shared__ double s_rho[R][kLanes];
-  __shared__ double s_psi[R][kLanes];
+  __shared__ C s_psi[R][kLanes];
   __shared__ C s_T[R][kLanes];
   __shared__ C s_ux[R][kLanes];
   __shared__ C s_uy[R][kLanes];
@@ -548,7 +553,7 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
       }
       s_rho[SA][lane] = rho;
       if constexpr (kRhoC) s_rc[SA][lane] = C(rho);
-      s_psi[SA][lane] = psi;
+      s_psi[SA][lane] = C(psi);
       s_T[SA][lane] = Tr;
     } else {
 #pragma unroll
@@ -566,20 +571,20 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
     const double rw = gld<GA>(A.tabd + (bottom ? 0 : 1) * nx + x);  // rho_w, or G_w (modified-psi)
     double psiw, rwall, psiwall;
     if (wall_mod) {
-      const double nbsum = s_psi[SN][lane] / 3.0 + (s_psi[SN][lp] + s_psi[SN][lm]) / 12.0;
+      const double nbsum = double(s_psi[SN][lane]) / 3.0 + (double(s_psi[SN][lp]) + double(s_psi[SN][lm])) / 12.0;
       rwall = wall_density_mod(K, nbsum, rw, Tw, sgn, P, rho_bar_k);
       psiwall = psi_checked(rwall, Tw, P, err);
       // solid neighbours seen by F^m: G psi psi_s = G_w psi^2
       psiw = rw / P.G * psiwall;
     } else {
       psiw = psi_checked(rw, Tw, P, err);
-      const double B = wall_coef_B(s_psi[SN][lane], s_psi[SN][lp], s_psi[SN][lm], psiw, sgn, P);
+      const double B = wall_coef_B(double(s_psi[SN][lane]), double(s_psi[SN][lp]), double(s_psi[SN][lm]), psiw, sgn, P);
       rwall = wall_density(K, B, Tw, sgn, P, rho_bar_k);
       psiwall = psi_checked(rwall, Tw, P, err);
     }
     s_rho[SW][lane] = rwall;
     if constexpr (kRhoC) s_rc[SW][lane] = C(rwall);
-    s_psi[SW][lane] = psiwall;
+    s_psi[SW][lane] = C(psiwall);
     if (bottom) psiw_b = psiw; else psiw_t = psiw;
   };
 
@@ -712,11 +717,11 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
     const bool wb = WALLS && ys == 0;
     const bool wt = WALLS && ys == ny - 1 && !outflow;
     const bool ot = WALLS && ys == ny - 1 && outflow;
-    const double pc = s_psi[kc][lane];
-    const double p1 = s_psi[kc][lp], p3 = s_psi[kc][lm];
-    double p2, p5, p6, p4, p7, p8;
+    const C pc = s_psi[kc][lane];
+    const C p1 = s_psi[kc][lp], p3 = s_psi[kc][lm];
+    C p2, p5, p6, p4, p7, p8;
     if (wt) {
-      p2 = p5 = p6 = psiw_t;
+      p2 = p5 = p6 = C(psiw_t);
     } else if (ot) {
       // zero-gradient outflow: psi above the top row is the top row's own
       p2 = pc;
@@ -728,40 +733,40 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
       p6 = s_psi[kq][lm];
     }
     if (wb) {
-      p4 = p7 = p8 = psiw_b;
+      p4 = p7 = p8 = C(psiw_b);
     } else {
       p4 = s_psi[km][lane];
       p7 = s_psi[km][lm];
       p8 = s_psi[km][lp];
     }
     const double rho = s_rho[kc][lane];
-    const double G = P.G;
+    const C G = C(P.G);
     // Eq. shanchen (psi_w for solid neighbours: Eq. shanchen-walls)
-    double d1 = p1 - pc, d2 = p2 - pc, d3 = p3 - pc, d4 = p4 - pc;
-    double d5 = p5 - pc, d6 = p6 - pc, d7 = p7 - pc, d8 = p8 - pc;
+    C d1 = p1 - pc, d2 = p2 - pc, d3 = p3 - pc, d4 = p4 - pc;
+    C d5 = p5 - pc, d6 = p6 - pc, d7 = p7 - pc, d8 = p8 - pc;
     if (WALLS && wall_mod) {
       // Eq. Q-mod-psi-based: solid neighbours drop out of Q
-      if (wb) d4 = d7 = d8 = 0.0;
-      if (wt) d2 = d5 = d6 = 0.0;
+      if (wb) d4 = d7 = d8 = C(0);
+      if (wt) d2 = d5 = d6 = C(0);
     }
-    const double sx = (1.0 / 3.0) * (p1 - p3) + (1.0 / 12.0) * ((p5 - p7) + (p8 - p6));
-    const double sy = (1.0 / 3.0) * (p2 - p4) + (1.0 / 12.0) * ((p5 - p7) + (p6 - p8));
-    const double fmx = -G * pc * sx;
-    const double fmy = -G * pc * sy;
-    const double fx = fmx;
-    const double fy = fmy + P.gy * (rho - rho_bar);
+    const C sx = C(1.0 / 3.0) * (p1 - p3) + C(1.0 / 12.0) * ((p5 - p7) + (p8 - p6));
+    const C sy = C(1.0 / 3.0) * (p2 - p4) + C(1.0 / 12.0) * ((p5 - p7) + (p6 - p8));
+    const C fmx = -G * pc * sx;
+    const C fmy = -G * pc * sy;
+    const C fx = fmx;
+    const C fy = fmy + C(P.gy * (rho - rho_bar));
     // Eq. Q / Q-psi-based
-    const double kq2 = P.kappa * G * 0.5 * pc;
-    const double dsum = (d5 + d6) + (d7 + d8);
-    const double qxx = kq2 * ((1.0 / 3.0) * (d1 + d3) + (1.0 / 12.0) * dsum);
-    const double qyy = kq2 * ((1.0 / 3.0) * (d2 + d4) + (1.0 / 12.0) * dsum);
-    const double qxy = kq2 * ((1.0 / 12.0) * ((d5 + d7) - (d6 + d8)));
+    const C kq2 = C(P.kappa * P.G * 0.5) * pc;
+    const C dsum = (d5 + d6) + (d7 + d8);
+    const C qxx = kq2 * (C(1.0 / 3.0) * (d1 + d3) + C(1.0 / 12.0) * dsum);
+    const C qyy = kq2 * (C(1.0 / 3.0) * (d2 + d4) + C(1.0 / 12.0) * dsum);
+    const C qxy = kq2 * (C(1.0 / 12.0) * ((d5 + d7) - (d6 + d8)));
 
     if (wb || wt) {
       // Zou-He reconstruction for the prescribed momentum -(F^m + F^b)/2,
       // the closure's buoyancy taken with rho_bar_k
-      jxs = C(-0.5 * fmx);
-      jys = C(-0.5 * (fmy + P.gy * (rho - rho_bar_k)));
+      jxs = C(-0.5) * fmx;
+      jys = C(-0.5) * (fmy + C(P.gy * (rho - rho_bar_k)));
       const C d = C(0.5) * (gp[1] - gp[3]);
       if (wb) {
         gp[2] = gp[4] + C(2.0 / 3.0) * jys;
@@ -773,10 +778,10 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
         gp[8] = gp[6] - d + C(0.5) * jxs - jys * C(1.0 / 6.0);
       }
     }
-    const double inv_rho = rcp64<kNR>(rho);
-    irho_out = C(inv_rho);
-    const double uxd = (double(jxs) + 0.5 * fx) * inv_rho;
-    const double uyd = (double(jys) + 0.5 * fy) * inv_rho;
+    const C inv_rho = rcp_c(C(rho));
+    irho_out = inv_rho;
+    const C uxd = (jxs + C(0.5) * fx) * inv_rho;
+    const C uyd = (jys + C(0.5) * fy) * inv_rho;
     s_ux[kc][lane] = C(uxd);
     s_uy[kc][lane] = C(uyd);
 
@@ -795,7 +800,7 @@ __device__ __forceinline__ void march_body(const StepArgs<S, C>& A, const MacroO
       ci[15] = C(rho);
       ci[16] = C(rho - rref);
       // sigma term 12 sigma |F^m|^2 / (psi^2 (tau - 1/2)) without the constant
-      ci[17] = C((fmx * fmx + fmy * fmy) * rcp64<kNR>(pc * pc));
+      ci[17] = (fmx * fmx + fmy * fmy) * rcp_c(pc * pc);
       ci[18] = C(qxx + qyy);
       ci[19] = C(qxx - qyy);
       ci[20] = C(qxy);
