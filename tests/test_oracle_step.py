@@ -344,6 +344,32 @@ def test_shear_wave_decay_gives_mrt_viscosity():
     assert abs(rate / (nu * k * k) - 1) < 0.01
 
 
+@pytest.mark.parametrize("rho0", [0.6, 1.0, 2.0])
+def test_shear_wave_viscosity_follows_density_interpolation(rho0):
+    """Eq. eta-rho (Sec. 'Physical dependence between meshes'): with
+    different phase viscosities, a shear wave in a uniform single-phase
+    state of density rho0 decays at the kinematic viscosity interpolated
+    linearly between eta_v at rho_v and eta_l at rho_l (weights
+    (rho0 - rho_v) and (rho_l - rho0) over rho_l - rho_v).  Swapped phases
+    or a wrong weight change the rate by far more than the 1 % tolerance."""
+    ny = 64
+    eta_l, eta_v = 0.12, 0.02
+    p = Params(nx=2, ny=ny, a=A, eta_l=eta_l, eta_v=eta_v, rho_l=RL, rho_v=RV)
+    s = Sim(p)
+    k = 2 * np.pi / ny
+    y = np.arange(ny)[:, None] * np.ones((1, 2))
+    U = 1e-4
+    s.init_fields(np.full((ny, 2), rho0), ux=U * np.sin(k * y), T=np.full((ny, 2), 1.2 * EOS.Tc))
+    amp = []
+    for _ in range(3):
+        s.step(200)
+        _, ux, _, _ = s.fields()
+        amp.append(2 / ny * np.sum(ux[:, 0] * np.sin(k * y[:, 0])))
+    rate = np.log(amp[0] / amp[2]) / 400
+    nu = eta_v + (eta_l - eta_v) * (rho0 - RV) / (RL - RV)
+    assert abs(rate / (nu * k * k) - 1) < 0.01
+
+
 def test_mass_conservation_periodic():
     c = wl.CONFIGS["droplet128"]
     n = 64
