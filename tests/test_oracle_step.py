@@ -287,6 +287,32 @@ def test_rk2_fourier_amplification():
                                atol=1e-9 * np.abs(dT).max())
 
 
+@pytest.mark.parametrize("rho0", [0.5, 1.0, 3.0])
+def test_rk2_amplification_uses_interpolated_conductivity(rho0):
+    """As above with different phase conductivities: over a uniform density
+    rho0 the diffusivity is lambda(rho0) / (rho0 c_v), with lambda linear in
+    rho between lambda_v at rho_v and lambda_l at rho_l (Sec. 2.3, the
+    conductivity rule beside Eq. energy-equation).  Swapped phases or a
+    wrong weight change z, and with it the one-step factor, well beyond the
+    tolerance."""
+    nx, ny = 16, 8
+    kx, ky = 2 * np.pi * 3 / nx, 2 * np.pi * 1 / ny
+    cv, lam_l, lam_v = 5.0, 0.8, 0.2
+    p = Params(nx=nx, ny=ny, a=A, rho_l=RL, rho_v=RV, thermal=True, cv=cv,
+               lambda_l=lam_l, lambda_v=lam_v)
+    s = Sim(p)
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    dT = 1e-6 * T86 * np.cos(kx * x + ky * y)
+    zero = np.zeros((ny, nx))
+    Tn = s.energy_update(T86 + dT, np.full((ny, nx), rho0), zero, zero)
+    lam = lam_v + (lam_l - lam_v) * (rho0 - RV) / (RL - RV)
+    alpha = lam / (rho0 * cv)
+    sym = (4 / 3) * (np.cos(kx) + np.cos(ky)) + (2 / 3) * np.cos(kx) * np.cos(ky) - 10 / 3
+    z = alpha * sym
+    np.testing.assert_allclose(Tn - T86, (1 + z + z * z / 2) * dT, rtol=0,
+                               atol=1e-9 * np.abs(dT).max())
+
+
 @pytest.mark.parametrize("ux,uy", [(0.05, 0.0), (0.0, -0.04), (0.03, 0.02), (-0.06, 0.035)])
 def test_rk2_fourier_amplification_with_uniform_flow(ux, uy):
     """Frozen uniform rho and uniform velocity u0 (so div u = 0 and the
