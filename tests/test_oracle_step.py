@@ -313,6 +313,33 @@ def test_rk2_amplification_uses_interpolated_conductivity(rho0):
                                atol=1e-9 * np.abs(dT).max())
 
 
+@pytest.mark.parametrize("rho0", [0.5, 2.0])
+def test_pressure_work_of_a_compressing_flow(rho0):
+    """Eq. energy-equation's pressure-work term on its own: uniform T and
+    rho (no conduction or advection of T to first order) and a frozen
+    velocity u = (eps sin(kx x), 0.7 eps sin(ky y)).  One step changes T by
+    -T (dp/dT)_rho div u / (rho c_v), with (dp/dT)_rho taken here by central
+    differences of the Peng-Robinson pressure and div u by the lattice
+    gradient's symbol (eps cos(kx x) sin kx + 0.7 eps cos(ky y) sin ky); the
+    midpoint RK2 adds only terms of order eps^2 and of the (tiny)
+    conductivity."""
+    nx, ny = 16, 8
+    kx, ky = 2 * np.pi * 2 / nx, 2 * np.pi / ny
+    cv, eps = 5.0, 1e-6
+    p = Params(nx=nx, ny=ny, a=A, rho_l=RL, rho_v=RV, thermal=True, cv=cv,
+               lambda_l=1e-4, lambda_v=1e-4)
+    s = Sim(p)
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    T = np.full((ny, nx), T86)
+    rho = np.full((ny, nx), rho0)
+    Tn = s.energy_update(T, rho, eps * np.sin(kx * x), 0.7 * eps * np.sin(ky * y))
+    h = 1e-5 * T86
+    dpdT = (EOS.p(rho0, T86 + h) - EOS.p(rho0, T86 - h)) / (2 * h)
+    divu = eps * (np.cos(kx * x) * np.sin(kx) + 0.7 * np.cos(ky * y) * np.sin(ky))
+    expect = -T86 * dpdT * divu / (rho0 * cv)
+    np.testing.assert_allclose(Tn - T, expect, rtol=0, atol=1e-4 * np.abs(expect).max())
+
+
 @pytest.mark.parametrize("ux,uy", [(0.05, 0.0), (0.0, -0.04), (0.03, 0.02), (-0.06, 0.035)])
 def test_rk2_fourier_amplification_with_uniform_flow(ux, uy):
     """Frozen uniform rho and uniform velocity u0 (so div u = 0 and the
